@@ -1,0 +1,148 @@
+/*
+ * swarmsf.h -- C ABI of the batched Swarm-Gen safety filter (SF) for MI355X (gfx950).
+ *
+ * The SF projects sampled joint swarm trajectories onto the set of trajectories that
+ * satisfy the boundary conditions (eq. boundary_con), pairwise collision avoidance
+ * (eq. inter_robot_con) and velocity/acceleration bounds, with the fixed-point
+ * iteration of the Appendix ("Custom SF optimizer", eqs. alpha_step .. xi_step):
+ * per-pair/per-time projections, the multiplier step, and an equality-constrained
+ * QP step against a factorisation computed once by sf_setup.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers unless marked "host".  The caller owns
+ *    them; the library never frees or retains them after the call returns.
+ *  - Coefficients are stored [sample][robot][axis][coeff], C order, contiguous.  In
+ *    a batch, problem p's samples follow problem p-1's, so problem p starts at
+ *    element sum_{q<p} count_q * n_q * D_q * m_q (m = degree + 1).
+ *  - Boundary values are [robot][axis][6] = (p0, v0, a0, pH, vH, aH) per problem,
+ *    packed in problem order (eq. boundary_con; both ends give position, velocity
+ *    and acceleration).
+ *  - Per-sample outputs are packed in sample order across problems.
+ *  - Precision SF_FP64: every floating-point array is double.  Otherwise every
+ *    floating-point array is float (SF_BF16 / SF_FP16 name the precision of the
+ *    fixed-matrix products inside the solver, not of the buffers).
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = default stream).
+ *  - Errors are returned as sf_status codes; nothing throws across the ABI.  The
+ *    message of the last error on the calling thread is sf_last_error().  On any
+ *    error nothing has been enqueued.
+ */
+#ifndef SWARMSF_H
+#define SWARMSF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sf_handle_s* sf_handle;
+
+typedef enum {
+  SF_OK = 0,
+  SF_EINVAL = 1,        /* bad argument: null pointer, size, shape, alignment */
+  SF_ENOMEM = 2,        /* device or host allocation failed */
+  SF_EDEVICE = 3,       /* a HIP runtime call failed */
+  SF_EUNSUPPORTED = 4   /* valid but outside what the kernels implement */
+} sf_status;
+
+typedef enum {
+  SF_FP64 = 0,          /* everything in double precision */
+  SF_FP32 = 1,          /* everything in single precision */
+  SF_BF16 = 2,          /* fixed-matrix products in bf16 MFMA + fp32 correction */
+  SF_FP16 = 3           /* fixed-matrix products in fp16 MFMA + fp32 correction */
+} sf_precision;
+
+/* Flags for sf_project. */
+#define SF_RESID_HISTORY 1   /* resid_out holds every iteration: [S][iters][2] */
+
+/* One problem shape (eqs. poly, inter_robot_con; bounds per the design notes).
+ *  n_robots >= 2, dims in {2, 3}, degree >= 5 (Bernstein), horizon >= degree + 1,
+ *  grid tau_h = h / (horizon - 1), h = 0..horizon-1, over [0, t_final] seconds.
+ *  safety_a, safety_b: semi-axes of the centre-to-centre spheroid M_a = diag(a, a, b)
+ *  (for spheres of radius r, a = b = 2r).  vmax, amax <= 0 switch that bound off.
+ *  rho_*: penalty weights of eq. aug_lag per constraint block (the paper uses one
+ *  rho; 1.0 for each block reproduces it). */
+typedef struct {
+  int32_t n_robots, dims, degree, horizon;
+  double t_final;
+  double safety_a, safety_b;
+  double vmax, amax;
+  double rho_coll, rho_vel, rho_acc;
+} sf_config;
+
+/* A batch of problems (host arrays of length n_problems).  cfg_slot indexes the
+ * configs given to sf_setup; sample_count >= 1 is the number of samples. */
+typedef struct {
+  int32_t n_problems;
+  const int32_t* cfg_slot;       /* host */
+  const int32_t* sample_count;   /* host */
+} sf_batch;
+
+/* Factorise the QP step of eq. (xi_step) for each config, in FP64 on the host, and
+ * upload the factors.  The KKT matrix does not depend on the samples (Appendix,
+ * "pre-stored factorisations"), so this runs once per shape.  Device memory owned by
+ * the handle is released by sf_destroy.  Selects the current HIP device. */
+sf_status sf_setup(const sf_config* cfgs, int32_t n_cfgs, sf_handle* out);
+
+void sf_destroy(sf_handle h);
+
+/* Run `iters` fixed-point iterations (eqs. alpha_step .. xi_step) on every sample.
+ *  xi_bar  [S, n, D, m]  sampled coefficients (the SF target)
+ *  bvals   [P, n, D, 6]  boundary values per problem
+ *  xi0     [S, n, D, m]  initial coefficients, or NULL for xi0 = xi_bar
+ *  lam0    [S, n, D, m]  initial multipliers, or NULL for zero
+ *  iters   >= 0
+ *  xi_out  [S, n, D, m]  result (may alias neither input)
+ *  lam_out [S, n, D, m]  final multipliers, or NULL
+ *  resid_out [S, 2] (or [S, iters, 2] with SF_RESID_HISTORY), or NULL:
+ *          (||r_p||_2^2, largest Euclidean norm of one constraint's residual block)
+ *          for the primal residual of eq. (primal_residual) after the last step.
+ *  ckpt    [ceil(iters/ckpt_every), 2, total coefficient elements] or NULL: the state
+ *          (xi^k, lambda^k) at k = 0, c, 2c, ... (c = ckpt_every >= 1), as needed by
+ *          sf_project_backward.
+ * Aliasing: outputs must not overlap inputs or each other. */
+sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision,
+                     const void* xi_bar, const void* bvals,
+                     const void* xi0, const void* lam0, int32_t iters,
+                     void* xi_out, void* lam_out, void* resid_out, int32_t flags,
+                     void* ckpt, int32_t ckpt_every, void* stream);
+
+/* Reverse-mode derivative of sf_project (same batch, precision, iters, xi_bar, bvals
+ * and the ckpt it wrote) through the unrolled iterations, eq. (NN_loss) style
+ * training of the initialisation.  Given cotangents of xi_out, lam_out and of
+ * resid_out[:, 0] (each may be NULL = zero) it writes the gradients with respect to
+ * xi0, lam0 and xi_bar (each may be NULL = not wanted).  g_resid is [S]. */
+sf_status sf_project_backward(sf_handle h, const sf_batch* batch, int32_t precision,
+                              const void* xi_bar, const void* bvals, int32_t iters,
+                              const void* ckpt, int32_t ckpt_every,
+                              const void* g_xi_out, const void* g_lam_out, const void* g_resid,
+                              void* g_xi0, void* g_lam0, void* g_xi_bar, void* stream);
+
+/* Constraint violations of coefficient arrays, computed in FP64 on the device at the
+ * grid times.  xi is [S, n, D, m] (double for SF_FP64, else float); viol_out is
+ * double [S, 4] = (a * (1 - min ||M_a^{-1}(p_i - p_j)||), max ||v|| - vmax,
+ * max ||acc|| - amax, max |A xi - b|); positive means violated. */
+sf_status sf_feasibility(sf_handle h, const sf_batch* batch, int32_t precision,
+                         const void* xi, const void* bvals, void* viol_out, void* stream);
+
+/* Host-only inspection of the FP64 factor table sf_setup builds for one config (needs no
+ * GPU).  Writes a 16-double header (m, m_f, H, n, then element offsets of basis, X1, X01,
+ * Bmap, Gfx, Rfx into the table that follows) and the table; *needed receives the
+ * number of doubles required (call with out = NULL to query).  Tables:
+ *   basis [3][H][m]  Bernstein position/velocity/acceleration rows at tau_h = h/(H-1)
+ *   X1  [m_f][m_f]   (I + n rho_c Gff + Rff)^-1,  X01 = (I + Rff)^-1 - X1, where
+ *                    G = P^T P, Rm = rho_v Pd^T Pd + rho_a Pdd^T Pdd, f = free coefficients
+ *                    3..degree-3: the free-coefficient block of the inverse KKT matrix of
+ *                    eq. (xi_step) is J (x) (X1 + X01) + (I - J) (x) X1 per axis, J = 11^T/n
+ *   Bmap [6][6]      pinned coefficients (c0, c1, c2, c_{N-2}, c_{N-1}, c_N) from b
+ *   Gfx, Rfx [m_f][6] free x pinned blocks of G and Rm. */
+sf_status sf_factor_table(const sf_config* cfg, double* out, int64_t capacity, int64_t* needed);
+
+/* Message of the last error returned on this thread ("" if none). */
+const char* sf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SWARMSF_H */

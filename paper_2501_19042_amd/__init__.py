@@ -1,0 +1,7 @@
+"""MI355X-native batched safety filter of Swarm-Gen (arXiv 2501.19042).
+
+The solver runs in the HIP kernels of libswarmsf.so (C ABI in include/swarmsf.h);
+this package marshals PyTorch device buffers and streams into that ABI.
+"""
+from .sf import Batch, ProjectResult, SafetyFilter, factor_table  # noqa: F401
+from . import _native  # noqa: F401

@@ -1,0 +1,493 @@
+// Host runtime of the safety filter: FP64 factorisation of the QP step, device tables,
+// batch plans, argument checks and kernel launches behind the C ABI of swarmsf.h.
+#include "swarmsf.h"
+#include "sf_internal.h"
+#include "sf_fast.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+sf_status fail(sf_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+sf_status hip_fail(hipError_t e, const char* what) {
+  return fail(SF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------------------------
+// FP64 host factorisation (eq. poly, eq. boundary_con, eq. xi_step)
+// ------------------------------------------------------------------------------------
+
+double binom(int n, int k) {
+  if (k < 0 || k > n) return 0.0;
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+double bern(int N, int k, double tau) {
+  if (N < 0 || k < 0 || k > N) return 0.0;
+  return binom(N, k) * std::pow(tau, k) * std::pow(1.0 - tau, N - k);
+}
+
+// In-place Gauss-Jordan inverse with partial pivoting; returns false if singular.
+bool invert(std::vector<double>& a, int n) {
+  std::vector<double> inv(n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[i * n + i] = 1.0;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(a[r * n + col]) > std::fabs(a[piv * n + col])) piv = r;
+    if (std::fabs(a[piv * n + col]) < 1e-300) return false;
+    if (piv != col)
+      for (int c = 0; c < n; ++c) {
+        std::swap(a[piv * n + c], a[col * n + c]);
+        std::swap(inv[piv * n + c], inv[col * n + c]);
+      }
+    const double d = a[col * n + col];
+    for (int c = 0; c < n; ++c) {
+      a[col * n + c] /= d;
+      inv[col * n + c] /= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double f = a[r * n + col];
+      if (f == 0.0) continue;
+      for (int c = 0; c < n; ++c) {
+        a[r * n + c] -= f * a[col * n + c];
+        inv[r * n + c] -= f * inv[col * n + c];
+      }
+    }
+  }
+  a.swap(inv);
+  return true;
+}
+
+struct HostCfg {
+  sf_config cfg;
+  sf::DevCfg dev;            // offsets relative to this config's table
+  std::vector<double> tab;
+};
+
+sf_status check_config(const sf_config& c) {
+  if (c.n_robots < 2) return fail(SF_EINVAL, "n_robots must be >= 2");
+  if (c.dims != 2 && c.dims != 3) return fail(SF_EINVAL, "dims must be 2 or 3");
+  if (c.degree < 5) return fail(SF_EINVAL, "degree must be >= 5 (six boundary rows per robot-axis)");
+  if (c.horizon < c.degree + 1) return fail(SF_EINVAL, "horizon must be >= degree + 1");
+  if (!(c.t_final > 0)) return fail(SF_EINVAL, "t_final must be > 0");
+  if (!(c.safety_a > 0) || !(c.safety_b > 0)) return fail(SF_EINVAL, "safety semi-axes must be > 0");
+  if (!(c.rho_coll > 0)) return fail(SF_EINVAL, "rho_coll must be > 0");
+  if (c.vmax > 0 && !(c.rho_vel > 0)) return fail(SF_EINVAL, "rho_vel must be > 0 when vmax > 0");
+  if (c.amax > 0 && !(c.rho_acc > 0)) return fail(SF_EINVAL, "rho_acc must be > 0 when amax > 0");
+  if (c.n_robots > 64) return fail(SF_EUNSUPPORTED, "n_robots > 64 is not supported");
+  if (c.degree > 30 || c.horizon > 4096) return fail(SF_EUNSUPPORTED, "degree > 30 or horizon > 4096");
+  return SF_OK;
+}
+
+sf_status build_cfg(const sf_config& c, HostCfg& out) {
+  sf_status st = check_config(c);
+  if (st != SF_OK) return st;
+  const int N = c.degree, m = N + 1, mf = m - sf::kNFix, H = c.horizon, n = c.n_robots;
+  const double T = c.t_final;
+  const bool vel = c.vmax > 0, acc = c.amax > 0;
+  std::vector<double> P(H * m), Pd(H * m), Pdd(H * m);
+  for (int h = 0; h < H; ++h) {
+    const double tau = (double)h / (H - 1);
+    for (int k = 0; k < m; ++k) {
+      P[h * m + k] = bern(N, k, tau);
+      Pd[h * m + k] = (N / T) * (bern(N - 1, k - 1, tau) - bern(N - 1, k, tau));
+      Pdd[h * m + k] = (N * (N - 1) / (T * T)) *
+                       (bern(N - 2, k - 2, tau) - 2.0 * bern(N - 2, k - 1, tau) + bern(N - 2, k, tau));
+    }
+  }
+  const int fix[sf::kNFix] = {0, 1, 2, m - 3, m - 2, m - 1};
+  const double* rows[sf::kNFix] = {&P[0], &Pd[0], &Pdd[0], &P[(H - 1) * m], &Pd[(H - 1) * m], &Pdd[(H - 1) * m]};
+  std::vector<double> Bmap(36);
+  for (int r = 0; r < 6; ++r) {
+    for (int k = 3; k < m - 3; ++k)
+      if (rows[r][k] != 0.0) return fail(SF_EINVAL, "boundary rows touch free coefficients");
+    for (int s = 0; s < 6; ++s) Bmap[r * 6 + s] = rows[r][fix[s]];
+  }
+  if (!invert(Bmap, 6)) return fail(SF_EINVAL, "boundary rows are singular");
+  // Gram matrices of the constraint blocks
+  std::vector<double> G(m * m, 0.0), Rm(m * m, 0.0);
+  for (int k = 0; k < m; ++k)
+    for (int l = 0; l < m; ++l) {
+      double g = 0, rv = 0, ra = 0;
+      for (int h = 0; h < H; ++h) {
+        g += P[h * m + k] * P[h * m + l];
+        rv += Pd[h * m + k] * Pd[h * m + l];
+        ra += Pdd[h * m + k] * Pdd[h * m + l];
+      }
+      G[k * m + l] = g;
+      Rm[k * m + l] = (vel ? c.rho_vel * rv : 0.0) + (acc ? c.rho_acc * ra : 0.0);
+    }
+  // Free-coefficient blocks of the KKT inverse: Z^T Q Z = J (x) (I + Rff) + (I - J) (x) (I + n rho Gff + Rff)
+  std::vector<double> X0(mf * mf), X1(mf * mf), X01(mf * mf), Gfx(mf * 6), Rfx(mf * 6);
+  for (int f = 0; f < mf; ++f)
+    for (int g2 = 0; g2 < mf; ++g2) {
+      const int k = 3 + f, l = 3 + g2;
+      const double id = (f == g2) ? 1.0 : 0.0;
+      X0[f * mf + g2] = id + Rm[k * m + l];
+      X1[f * mf + g2] = id + n * c.rho_coll * G[k * m + l] + Rm[k * m + l];
+    }
+  if (mf > 0 && (!invert(X0, mf) || !invert(X1, mf))) return fail(SF_EINVAL, "QP block is singular");
+  for (int q = 0; q < mf * mf; ++q) X01[q] = X0[q] - X1[q];
+  for (int f = 0; f < mf; ++f)
+    for (int r = 0; r < 6; ++r) {
+      Gfx[f * 6 + r] = G[(3 + f) * m + fix[r]];
+      Rfx[f * 6 + r] = Rm[(3 + f) * m + fix[r]];
+    }
+  sf::DevCfg& d = out.dev;
+  std::memset(&d, 0, sizeof(d));
+  d.n = n; d.D = c.dims; d.m = m; d.mf = mf; d.H = H; d.Np = n * (n - 1) / 2;
+  d.vel_on = vel; d.acc_on = acc;
+  d.a = c.safety_a; d.b = c.safety_b;
+  d.inv_a2 = 1.0 / (c.safety_a * c.safety_a);
+  d.inv_b2 = 1.0 / (c.safety_b * c.safety_b);
+  d.vmax = vel ? c.vmax : 0.0; d.amax = acc ? c.amax : 0.0;
+  d.rho_c = c.rho_coll; d.rho_v = vel ? c.rho_vel : 0.0; d.rho_a = acc ? c.rho_acc : 0.0;
+  d.n_rho_c = n * c.rho_coll;
+  std::vector<double>& t = out.tab;
+  t.clear();
+  d.off_basis = t.size();
+  t.insert(t.end(), P.begin(), P.end());
+  t.insert(t.end(), Pd.begin(), Pd.end());
+  t.insert(t.end(), Pdd.begin(), Pdd.end());
+  d.off_X1 = t.size(); t.insert(t.end(), X1.begin(), X1.end());
+  d.off_X01 = t.size(); t.insert(t.end(), X01.begin(), X01.end());
+  d.off_Bmap = t.size(); t.insert(t.end(), Bmap.begin(), Bmap.end());
+  d.off_Gfx = t.size(); t.insert(t.end(), Gfx.begin(), Gfx.end());
+  d.off_Rfx = t.size(); t.insert(t.end(), Rfx.begin(), Rfx.end());
+  while (t.size() % 64) t.push_back(0.0);   // keep each config's table 512-byte aligned
+  out.cfg = c;
+  return SF_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Batch plans: problem table and work items on the device, cached per batch.
+// ------------------------------------------------------------------------------------
+
+struct Plan {
+  std::vector<int32_t> key;
+  sf::DevProblem* d_probs = nullptr;
+  sf::WorkItem* d_items = nullptr;
+  int32_t n_items = 0;
+  int64_t total_samples = 0, total_coef = 0, total_bnd = 0;
+  std::vector<sf::DevProblem> probs;
+  std::vector<int32_t> slots_used;
+  sf::FastPlan fast;            // MFMA-path plan (empty if not applicable)
+};
+
+}  // namespace
+
+struct sf_handle_s {
+  int device = 0;
+  std::vector<HostCfg> cfgs;
+  sf::DevCfg* d_cfgs = nullptr;
+  double* d_tab64 = nullptr;
+  float* d_tab32 = nullptr;
+  std::vector<Plan*> plans;
+  std::mutex mu;
+};
+
+namespace {
+
+void free_plan(Plan* p) {
+  if (!p) return;
+  if (p->d_probs) (void)hipFree(p->d_probs);
+  if (p->d_items) (void)hipFree(p->d_items);
+  sf::fast_plan_free(p->fast);
+  delete p;
+}
+
+sf_status get_plan(sf_handle h, const sf_batch* batch, Plan** out) {
+  if (!batch) return fail(SF_EINVAL, "batch is NULL");
+  if (batch->n_problems < 1) return fail(SF_EINVAL, "batch has no problems");
+  if (!batch->cfg_slot || !batch->sample_count) return fail(SF_EINVAL, "batch arrays are NULL");
+  std::vector<int32_t> key(2 * (size_t)batch->n_problems);
+  for (int p = 0; p < batch->n_problems; ++p) {
+    const int32_t s = batch->cfg_slot[p], cnt = batch->sample_count[p];
+    if (s < 0 || s >= (int)h->cfgs.size()) return fail(SF_EINVAL, "cfg_slot out of range");
+    if (cnt < 1) return fail(SF_EINVAL, "sample_count must be >= 1");
+    key[2 * p] = s;
+    key[2 * p + 1] = cnt;
+  }
+  for (size_t i = 0; i < h->plans.size(); ++i)
+    if (h->plans[i]->key == key) {
+      Plan* p = h->plans[i];
+      h->plans.erase(h->plans.begin() + i);
+      h->plans.insert(h->plans.begin(), p);   // most recently used first
+      *out = p;
+      return SF_OK;
+    }
+  Plan* p = new Plan();
+  p->key = key;
+  std::vector<sf::WorkItem> items;
+  std::vector<bool> used(h->cfgs.size(), false);
+  int64_t coef = 0, bnd = 0, smp = 0;
+  for (int q = 0; q < batch->n_problems; ++q) {
+    const sf::DevCfg& c = h->cfgs[key[2 * q]].dev;
+    sf::DevProblem pr;
+    pr.cfg = key[2 * q];
+    pr.count = key[2 * q + 1];
+    pr.coef_off = coef;
+    pr.bnd_off = bnd;
+    pr.sample_base = smp;
+    p->probs.push_back(pr);
+    used[pr.cfg] = true;
+    for (int s = 0; s < pr.count; ++s) items.push_back(sf::WorkItem{q, s, 1, 0});
+    coef += (int64_t)pr.count * c.n * c.D * c.m;
+    bnd += (int64_t)c.n * c.D * sf::kNFix;
+    smp += pr.count;
+  }
+  for (size_t s = 0; s < used.size(); ++s)
+    if (used[s]) p->slots_used.push_back((int32_t)s);
+  if (items.size() > (size_t)INT32_MAX) {
+    free_plan(p);
+    return fail(SF_EUNSUPPORTED, "too many samples in one batch");
+  }
+  p->n_items = (int32_t)items.size();
+  p->total_samples = smp;
+  p->total_coef = coef;
+  p->total_bnd = bnd;
+  hipError_t e = hipMalloc(&p->d_probs, p->probs.size() * sizeof(sf::DevProblem));
+  if (e == hipSuccess) e = hipMalloc(&p->d_items, items.size() * sizeof(sf::WorkItem));
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_probs, p->probs.data(), p->probs.size() * sizeof(sf::DevProblem), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(sf::WorkItem), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return hip_fail(e, "plan upload");
+  }
+  std::vector<sf::DevCfg> cfgs;
+  for (auto& hc : h->cfgs) cfgs.push_back(hc.dev);
+  sf_status st = sf::fast_plan_build(cfgs, p->probs, p->fast);
+  if (st != SF_OK) {
+    free_plan(p);
+    return fail(st, "fast plan: " + sf::fast_last_error());
+  }
+  if (h->plans.size() >= 8) {
+    free_plan(h->plans.back());
+    h->plans.pop_back();
+  }
+  h->plans.insert(h->plans.begin(), p);
+  *out = p;
+  return SF_OK;
+}
+
+// Largest time tile (<= 32) whose LDS plan fits every config of the plan.
+sf_status pick_tile(sf_handle h, const Plan* p, size_t elem, size_t (*bytes)(const sf::DevCfg&, int, size_t),
+                    int* tile, size_t* lds) {
+  int maxH = 1;
+  for (int32_t s : p->slots_used) maxH = std::max(maxH, h->cfgs[s].dev.H);
+  for (int TT = std::min(32, maxH); TT >= 1; TT = (TT > 4 ? TT / 2 : TT - 1)) {
+    size_t worst = 0;
+    for (int32_t s : p->slots_used) worst = std::max(worst, bytes(h->cfgs[s].dev, TT, elem));
+    if (worst <= 80 * 1024 || (TT == 1 && worst <= 160 * 1024)) {
+      *tile = TT;
+      *lds = worst;
+      return SF_OK;
+    }
+  }
+  return fail(SF_EUNSUPPORTED, "problem does not fit the LDS plan");
+}
+
+size_t generic_bytes(const sf::DevCfg& c, int tile, size_t elem) { return sf::generic_lds_bytes(c, tile, elem); }
+size_t feas_bytes(const sf::DevCfg& c, int tile, size_t) { return sf::feasibility_lds_bytes(c, tile); }
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+sf_status check_device(sf_handle h) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != h->device) return fail(SF_EINVAL, "current device differs from the handle's device");
+  return SF_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------
+// C ABI
+// ------------------------------------------------------------------------------------
+
+extern "C" {
+
+const char* sf_last_error(void) { return g_err.c_str(); }
+
+sf_status sf_factor_table(const sf_config* cfg, double* out, int64_t capacity, int64_t* needed) {
+  g_err.clear();
+  if (!cfg || !needed) return fail(SF_EINVAL, "cfg/needed is NULL");
+  HostCfg hc;
+  sf_status st = build_cfg(*cfg, hc);
+  if (st != SF_OK) return st;
+  const int64_t header = 16;
+  *needed = header + (int64_t)hc.tab.size();
+  if (!out) return SF_OK;
+  if (capacity < *needed) return fail(SF_EINVAL, "capacity too small");
+  const sf::DevCfg& d = hc.dev;
+  const double hdr[16] = {(double)d.m, (double)d.mf, (double)d.H, (double)d.n,
+                          (double)d.off_basis, (double)d.off_X1, (double)d.off_X01, (double)d.off_Bmap,
+                          (double)d.off_Gfx, (double)d.off_Rfx, 0, 0, 0, 0, 0, 0};
+  std::memcpy(out, hdr, sizeof(hdr));
+  std::memcpy(out + header, hc.tab.data(), hc.tab.size() * sizeof(double));
+  return SF_OK;
+}
+
+sf_status sf_setup(const sf_config* cfgs, int32_t n_cfgs, sf_handle* out) {
+  g_err.clear();
+  if (!cfgs || !out || n_cfgs < 1) return fail(SF_EINVAL, "sf_setup: bad arguments");
+  *out = nullptr;
+  sf_handle h = new sf_handle_s();
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "hipGetDevice");
+  }
+  std::vector<double> all;
+  std::vector<sf::DevCfg> devs;
+  for (int i = 0; i < n_cfgs; ++i) {
+    HostCfg hc;
+    sf_status st = build_cfg(cfgs[i], hc);
+    if (st != SF_OK) {
+      delete h;
+      return fail(st, "config " + std::to_string(i) + ": " + g_err);
+    }
+    const int64_t base = all.size();
+    sf::DevCfg d = hc.dev;
+    d.off_basis += base; d.off_X1 += base; d.off_X01 += base;
+    d.off_Bmap += base; d.off_Gfx += base; d.off_Rfx += base;
+    all.insert(all.end(), hc.tab.begin(), hc.tab.end());
+    hc.dev = d;
+    devs.push_back(d);
+    h->cfgs.push_back(std::move(hc));
+  }
+  std::vector<float> all32(all.begin(), all.end());
+  e = hipMalloc(&h->d_cfgs, devs.size() * sizeof(sf::DevCfg));
+  if (e == hipSuccess) e = hipMalloc(&h->d_tab64, all.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&h->d_tab32, all32.size() * sizeof(float));
+  if (e == hipSuccess) e = hipMemcpy(h->d_cfgs, devs.data(), devs.size() * sizeof(sf::DevCfg), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->d_tab64, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->d_tab32, all32.data(), all32.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    sf_destroy(h);
+    return hip_fail(e, "sf_setup upload");
+  }
+  *out = h;
+  return SF_OK;
+}
+
+void sf_destroy(sf_handle h) {
+  if (!h) return;
+  for (Plan* p : h->plans) free_plan(p);
+  if (h->d_cfgs) (void)hipFree(h->d_cfgs);
+  if (h->d_tab64) (void)hipFree(h->d_tab64);
+  if (h->d_tab32) (void)hipFree(h->d_tab32);
+  delete h;
+}
+
+sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, const void* xi_bar,
+                     const void* bvals, const void* xi0, const void* lam0, int32_t iters, void* xi_out,
+                     void* lam_out, void* resid_out, int32_t flags, void* ckpt, int32_t ckpt_every,
+                     void* stream) {
+  g_err.clear();
+  if (!h) return fail(SF_EINVAL, "handle is NULL");
+  if (precision < SF_FP64 || precision > SF_FP16) return fail(SF_EINVAL, "unknown precision");
+  if (!xi_bar || !bvals || !xi_out) return fail(SF_EINVAL, "xi_bar, bvals and xi_out are required");
+  if (iters < 0) return fail(SF_EINVAL, "iters must be >= 0");
+  if (flags & ~SF_RESID_HISTORY) return fail(SF_EINVAL, "unknown flags");
+  if (ckpt && ckpt_every < 1) return fail(SF_EINVAL, "ckpt_every must be >= 1 with a checkpoint buffer");
+  const size_t elem = precision == SF_FP64 ? sizeof(double) : sizeof(float);
+  const void* ptrs[] = {xi_bar, bvals, xi0, lam0, xi_out, lam_out, resid_out, ckpt};
+  for (const void* q : ptrs)
+    if (q && !aligned(q, elem)) return fail(SF_EINVAL, "misaligned array");
+  std::lock_guard<std::mutex> lock(h->mu);
+  sf_status st = check_device(h);
+  if (st != SF_OK) return st;
+  Plan* p = nullptr;
+  st = get_plan(h, batch, &p);
+  if (st != SF_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  sf::LaunchArgs a{};
+  a.cfgs = h->d_cfgs;
+  a.probs = p->d_probs;
+  a.items = p->d_items;
+  a.n_items = p->n_items;
+  a.xi_bar = xi_bar; a.bvals = bvals; a.xi0 = xi0; a.lam0 = lam0; a.iters = iters;
+  a.xi_out = xi_out; a.lam_out = lam_out; a.resid_out = resid_out; a.flags = flags;
+  a.ckpt = ckpt; a.ckpt_every = ckpt ? ckpt_every : 1; a.ckpt_stride = p->total_coef;
+  a.stream = s;
+  hipError_t e;
+  if (precision == SF_FP64) {
+    a.tab = h->d_tab64;
+    st = pick_tile(h, p, sizeof(double), generic_bytes, &a.tile, &a.lds_bytes);
+    if (st != SF_OK) return st;
+    e = sf::launch_generic_project<double>(a);
+  } else {
+    a.tab = h->d_tab32;
+    const bool want_fast = p->fast.ok && !(flags & SF_RESID_HISTORY);
+    if (precision != SF_FP32 && !want_fast)
+      return fail(SF_EUNSUPPORTED, "the MFMA precisions need a batch the MFMA kernels cover "
+                                   "(3D, supported swarm sizes) and no residual history");
+    if (want_fast) {
+      e = sf::fast_launch(p->fast, a, h->d_tab32, precision);
+    } else {
+      st = pick_tile(h, p, sizeof(float), generic_bytes, &a.tile, &a.lds_bytes);
+      if (st != SF_OK) return st;
+      e = sf::launch_generic_project<float>(a);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(e, "sf_project launch");
+  return SF_OK;
+}
+
+sf_status sf_project_backward(sf_handle h, const sf_batch* batch, int32_t precision, const void* xi_bar,
+                              const void* bvals, int32_t iters, const void* ckpt, int32_t ckpt_every,
+                              const void* g_xi_out, const void* g_lam_out, const void* g_resid,
+                              void* g_xi0, void* g_lam0, void* g_xi_bar, void* stream) {
+  g_err.clear();
+  (void)h; (void)batch; (void)precision; (void)xi_bar; (void)bvals; (void)iters; (void)ckpt;
+  (void)ckpt_every; (void)g_xi_out; (void)g_lam_out; (void)g_resid; (void)g_xi0; (void)g_lam0;
+  (void)g_xi_bar; (void)stream;
+  return fail(SF_EUNSUPPORTED, "sf_project_backward is not available yet");
+}
+
+sf_status sf_feasibility(sf_handle h, const sf_batch* batch, int32_t precision, const void* xi,
+                         const void* bvals, void* viol_out, void* stream) {
+  g_err.clear();
+  if (!h) return fail(SF_EINVAL, "handle is NULL");
+  if (!xi || !bvals || !viol_out) return fail(SF_EINVAL, "xi, bvals and viol_out are required");
+  if (precision < SF_FP64 || precision > SF_FP16) return fail(SF_EINVAL, "unknown precision");
+  const size_t elem = precision == SF_FP64 ? sizeof(double) : sizeof(float);
+  if (!aligned(xi, elem) || !aligned(bvals, elem) || !aligned(viol_out, sizeof(double)))
+    return fail(SF_EINVAL, "misaligned array");
+  std::lock_guard<std::mutex> lock(h->mu);
+  sf_status st = check_device(h);
+  if (st != SF_OK) return st;
+  Plan* p = nullptr;
+  st = get_plan(h, batch, &p);
+  if (st != SF_OK) return st;
+  int tile = 0;
+  size_t lds = 0;
+  st = pick_tile(h, p, sizeof(double), feas_bytes, &tile, &lds);
+  if (st != SF_OK) return st;
+  hipError_t e = sf::launch_feasibility(h->d_cfgs, h->d_tab64, p->d_probs, p->d_items, p->n_items, xi,
+                                        precision == SF_FP64, bvals, static_cast<double*>(viol_out), tile, lds,
+                                        static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "sf_feasibility launch");
+  return SF_OK;
+}
+
+}  // extern "C"

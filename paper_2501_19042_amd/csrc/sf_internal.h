@@ -1,0 +1,76 @@
+// Internal types shared by the host runtime and the kernels of the safety filter.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace sf {
+
+constexpr int kBlock = 256;          // threads per workgroup of the generic kernels
+constexpr int kNFix = 6;             // coefficients pinned by the boundary rows per robot-axis
+
+// Per-config constants on the device.  Matrices live in a per-precision table; the
+// offsets below are element offsets into it.
+//   basis [3][H][m]   position, velocity, acceleration Bernstein rows (eq. poly)
+//   X1    [mf][mf]    (I + n rho_c Gff + Rff)^-1    relative-motion block of the QP step
+//   X01   [mf][mf]    (I + Rff)^-1 - X1             mean-motion minus relative block
+//   Bmap  [6][6]      pinned coefficients (c0, c1, c2, c_{N-2}, c_{N-1}, c_N) from
+//                     (p0, v0, a0, pH, vH, aH)
+//   Gfx   [mf][6]     G = P^T P, free rows x pinned columns
+//   Rfx   [mf][6]     Rm = rho_v Pd^T Pd + rho_a Pdd^T Pdd, free rows x pinned columns
+struct DevCfg {
+  int32_t n, D, m, mf, H, Np;
+  int32_t vel_on, acc_on;
+  double a, b, inv_a2, inv_b2, vmax, amax;
+  double rho_c, rho_v, rho_a, n_rho_c;
+  int64_t off_basis, off_X1, off_X01, off_Bmap, off_Gfx, off_Rfx;
+};
+
+struct DevProblem {
+  int32_t cfg, count;
+  int64_t coef_off;      // element offset of the problem's first coefficient
+  int64_t bnd_off;       // element offset of its boundary values
+  int64_t sample_base;   // global index of its first sample
+};
+
+struct WorkItem {
+  int32_t problem, first, count, pad;
+};
+
+struct LaunchArgs {
+  const DevCfg* cfgs;
+  const void* tab;               // per-precision constant table
+  const DevProblem* probs;
+  const WorkItem* items;
+  int32_t n_items;
+  const void* xi_bar;
+  const void* bvals;
+  const void* xi0;
+  const void* lam0;
+  int32_t iters;
+  void* xi_out;
+  void* lam_out;
+  void* resid_out;
+  int32_t flags;
+  void* ckpt;
+  int32_t ckpt_every;
+  int64_t ckpt_stride;           // total coefficient elements of the batch
+  int32_t tile;                  // time-tile length
+  size_t lds_bytes;
+  hipStream_t stream;
+};
+
+// Generic fused kernels (any shape that fits the LDS plan), T = double or float.
+template <typename T>
+hipError_t launch_generic_project(const LaunchArgs& a);
+
+hipError_t launch_feasibility(const DevCfg* cfgs, const double* tab64, const DevProblem* probs,
+                              const WorkItem* items, int32_t n_items, const void* xi, int xi_is_double,
+                              const void* bvals, double* viol, int32_t tile, size_t lds_bytes,
+                              hipStream_t stream);
+
+// LDS bytes needed by the generic kernel for one config at a given time tile.
+size_t generic_lds_bytes(const DevCfg& c, int tile, size_t elem);
+size_t feasibility_lds_bytes(const DevCfg& c, int tile);
+
+}  // namespace sf
