@@ -61,7 +61,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="swarm16", choices=["swarm16", "swarm32", "tiny2d"])
     ap.add_argument("--precision", default="fp32")
-    ap.add_argument("--cpu-samples", type=int, default=32)
+    ap.add_argument("--cpu-samples", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
