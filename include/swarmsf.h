@@ -55,6 +55,7 @@ typedef enum {
 
 /* Flags for sf_project. */
 #define SF_RESID_HISTORY 1   /* resid_out holds every iteration: [S][iters][2] */
+#define SF_GENERIC_KERNEL 2  /* use the generic LDS kernel even where the MFMA kernel applies */
 
 /* One problem shape (eqs. poly, inter_robot_con; bounds per the design notes).
  *  n_robots >= 2, dims in {2, 3}, degree >= 5 (Bernstein), horizon >= degree + 1,

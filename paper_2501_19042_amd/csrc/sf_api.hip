@@ -407,7 +407,7 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
   if (precision < SF_FP64 || precision > SF_FP16) return fail(SF_EINVAL, "unknown precision");
   if (!xi_bar || !bvals || !xi_out) return fail(SF_EINVAL, "xi_bar, bvals and xi_out are required");
   if (iters < 0) return fail(SF_EINVAL, "iters must be >= 0");
-  if (flags & ~SF_RESID_HISTORY) return fail(SF_EINVAL, "unknown flags");
+  if (flags & ~(SF_RESID_HISTORY | SF_GENERIC_KERNEL)) return fail(SF_EINVAL, "unknown flags");
   if (ckpt && ckpt_every < 1) return fail(SF_EINVAL, "ckpt_every must be >= 1 with a checkpoint buffer");
   const size_t elem = precision == SF_FP64 ? sizeof(double) : sizeof(float);
   const void* ptrs[] = {xi_bar, bvals, xi0, lam0, xi_out, lam_out, resid_out, ckpt};
@@ -426,7 +426,7 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
   a.items = p->d_items;
   a.n_items = p->n_items;
   a.xi_bar = xi_bar; a.bvals = bvals; a.xi0 = xi0; a.lam0 = lam0; a.iters = iters;
-  a.xi_out = xi_out; a.lam_out = lam_out; a.resid_out = resid_out; a.flags = flags;
+  a.xi_out = xi_out; a.lam_out = lam_out; a.resid_out = resid_out; a.flags = flags & SF_RESID_HISTORY;
   a.ckpt = ckpt; a.ckpt_every = ckpt ? ckpt_every : 1; a.ckpt_stride = p->total_coef;
   a.stream = s;
   hipError_t e;
@@ -437,7 +437,7 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
     e = sf::launch_generic_project<double>(a);
   } else {
     a.tab = h->d_tab32;
-    const bool want_fast = p->fast.ok && !(flags & SF_RESID_HISTORY);
+    const bool want_fast = p->fast.ok && !(flags & (SF_RESID_HISTORY | SF_GENERIC_KERNEL));
     if (precision != SF_FP32 && !want_fast)
       return fail(SF_EUNSUPPORTED, "the MFMA precisions need a batch the MFMA kernels cover "
                                    "(3D, supported swarm sizes) and no residual history");

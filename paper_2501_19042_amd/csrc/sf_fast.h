@@ -11,6 +11,10 @@ namespace sf {
 
 struct FastPlan {
   bool ok = false;              // the batch is covered by the fast kernels
+  int R = 0;                    // robot tiles of 16
+  int KS = 0;                   // k-steps of 4 coefficients
+  int TQ = 0;                   // time tiles per wave
+  size_t lds_bytes = 0;
 };
 
 sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<DevProblem>& probs, FastPlan& out);

@@ -96,7 +96,7 @@ class SafetyFilter:
     def project(self, xi_bar: torch.Tensor, bvals: torch.Tensor, iters: int, batch: Optional[Batch] = None,
                 precision: str = "fp32", xi0: Optional[torch.Tensor] = None, lam0: Optional[torch.Tensor] = None,
                 want_lam: bool = True, want_resid: bool = True, history: bool = False,
-                ckpt_every: int = 0, stream=None) -> ProjectResult:
+                ckpt_every: int = 0, generic: bool = False, stream=None) -> ProjectResult:
         prec = N.PRECISIONS[precision]
         dtype = torch.float64 if prec == N.SF_FP64 else torch.float32
         batch = self._batch(batch, xi_bar)
@@ -112,7 +112,7 @@ class SafetyFilter:
         if ckpt_every:
             nck = max(1, math.ceil(iters / ckpt_every))
             ckpt = torch.empty((nck, 2, coef), dtype=dtype, device=self.device)
-        flags = N.SF_RESID_HISTORY if history else 0
+        flags = (N.SF_RESID_HISTORY if history else 0) | (N.SF_GENERIC_KERNEL if generic else 0)
         N.check(N.lib().sf_project(self._h, ctypes.byref(batch.c), prec, _ptr(xi_bar), _ptr(bvals), _ptr(xi0),
                                    _ptr(lam0), int(iters), _ptr(xi_out), _ptr(lam_out), _ptr(resid), flags,
                                    _ptr(ckpt), int(ckpt_every), _stream_ptr(stream)))

@@ -215,12 +215,12 @@ def test_ragged_batch_equals_separate_calls(lib):
         batch = P.Batch([(i, p.xi_bar.shape[0]) for i, p in enumerate(probs)])
         xb = torch.cat([torch.as_tensor(p.xi_bar, dtype=dt).reshape(-1) for p in probs]).cuda()
         bv = torch.cat([torch.as_tensor(p.bvals, dtype=dt).reshape(-1) for p in probs]).cuda()
-        out = sf.project(xb, bv, 30, batch=batch, precision=prec)
+        out = sf.project(xb, bv, 30, batch=batch, precision=prec, generic=True)
         torch.cuda.synchronize()
         o = 0
         r0 = 0
         for i, p in enumerate(probs):
-            single = gpu_run(P, p.cfg, p.xi_bar, p.bvals, 30, prec)
+            single = gpu_run(P, p.cfg, p.xi_bar, p.bvals, 30, prec, generic=True)
             nel = p.xi_bar.size
             assert torch.equal(out.xi[o:o + nel].cpu(), single.xi.reshape(-1).cpu())
             S = p.xi_bar.shape[0]
