@@ -102,7 +102,7 @@ __device__ __forceinline__ void coll_resid3(float rx, float ry, float rz, float 
 }
 
 template <int R, int KS, int W, int TQ>
-__global__ void __launch_bounds__(64 * W)
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2, 2)))
 fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ tab,
                     const DevProblem* __restrict__ probs, const WorkItem* __restrict__ items, int n_items,
                     const float* __restrict__ xi_bar, const float* __restrict__ bvals,
@@ -111,6 +111,7 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
                     float* __restrict__ ckpt, int ckpt_every, int64_t ckpt_stride) {
   extern __shared__ __align__(16) float smem[];
   constexpr int NR = 16 * R;
+  constexpr int PR = (NR * (NR - 1) / 2 + 63) / 64;   // 64-pair rounds of the broad phase
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int nthr = 64 * W;
@@ -158,8 +159,8 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
       int p = i * n - i * (i + 1) / 2;
       for (int j = i + 1; j < n; ++j) spairs[p++] = i | (j << 8);
     }
-    // loop-invariant MFMA operands of this wave's tiles: S1 A (basis rows), S4 B (rho_b * basis)
-    float a1[TQ][3][KS], b4[TQ][3][4];
+    // loop-invariant MFMA A operands of this wave's tiles (basis rows of S1)
+    float a1[TQ][3][KS];
     const float rho[3] = {(float)c.rho_c, (float)c.rho_v, (float)c.rho_a};
 #pragma unroll
     for (int q = 0; q < TQ; ++q) {
@@ -171,13 +172,13 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
           const int t = t0 + col, k = 4 * s + grp;
           a1[q][b][s] = (t < H && k < m) ? basis[((size_t)b * H + t) * m + k] : 0.0f;
         }
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int t = t0 + 4 * grp + s;
-          b4[q][b][s] = (t < H && col < m) ? rho[b] * basis[((size_t)b * H + t) * m + col] : 0.0f;
-        }
       }
     }
+
+    __syncthreads();
+    int mypair[PR];
+#pragma unroll
+    for (int r = 0; r < PR; ++r) mypair[r] = (64 * r + lane < Np) ? spairs[64 * r + lane] : -1;
 
     for (int sl = w.first; sl < w.first + w.count; ++sl) {
       const int64_t coef = pr.coef_off + (int64_t)sl * nDm;
@@ -253,52 +254,73 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
           if (tau >= NT) break;
           const int t0 = 16 * tau;
           const int nt = min(16, H - t0);
-          // ---- S1 ----
-          f4 Y[R][3][3];
+          // ---- S1 positions -> LDS ----
+          {
+            f4 Y[R][3];
 #pragma unroll
-          for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
+            for (int rr = 0; rr < R; ++rr)
 #pragma unroll
               for (int d = 0; d < 3; ++d) {
                 f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                for (int s = 0; s < KS; ++s) acc = mfma4(a1[q][b][s], bx[rr][d][s], acc);
-                Y[rr][b][d] = acc;
+                for (int s = 0; s < KS; ++s) acc = mfma4(a1[q][0][s], bx[rr][d][s], acc);
+                Y[rr][d] = acc;
               }
-          // ---- S3: bound balls in registers ----
-          bool nzv = false, nza = false;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+              for (int d = 0; d < 3; ++d) {
+                const int o = (d * NR + 16 * rr + col) * 16 + 4 * grp;
+                *reinterpret_cast<f4*>(Xt + o) = Y[rr][d];
+                *reinterpret_cast<f4*>(Ct + o) = f4{0.0f, 0.0f, 0.0f, 0.0f};
+              }
+          }
+          // ---- S1 velocity / acceleration, S3 bound balls in registers, S4 for nonzero tiles ----
 #pragma unroll
           for (int b = 1; b < 3; ++b) {
             const bool on = b == 1 ? c.vel_on : c.acc_on;
             if (!on) continue;
             const float lim = b == 1 ? vmax : amax;
+            f4 Y[R][3];
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+              for (int d = 0; d < 3; ++d) {
+                f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int s = 0; s < KS; ++s) acc = mfma4(a1[q][b][s], bx[rr][d][s], acc);
+                Y[rr][d] = acc;
+              }
+            bool nz = false;
 #pragma unroll
             for (int rr = 0; rr < R; ++rr)
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                const float vx = Y[rr][b][0][r], vy = Y[rr][b][1][r], vz = Y[rr][b][2][r];
+                const float vx = Y[rr][0][r], vy = Y[rr][1][r], vz = Y[rr][2][r];
                 const float ss = vx * vx + vy * vy + vz * vz;
                 const float f = ss > lim * lim ? 1.0f - lim * rsqrtf(ss) : 0.0f;
-                Y[rr][b][0][r] = f * vx;
-                Y[rr][b][1][r] = f * vy;
-                Y[rr][b][2][r] = f * vz;
-                if (b == 1) nzv |= f != 0.0f;
-                else nza |= f != 0.0f;
+                Y[rr][0][r] = f * vx;
+                Y[rr][1][r] = f * vy;
+                Y[rr][2][r] = f * vz;
+                nz |= f != 0.0f;
               }
-          }
-          nzv = ballot(nzv) != 0;
-          nza = ballot(nza) != 0;
-          // ---- S2: positions to LDS, broad phase, narrow phase ----
+            if (ballot(nz) != 0) {
+              float b4[4];
 #pragma unroll
-          for (int rr = 0; rr < R; ++rr)
+              for (int s = 0; s < 4; ++s) {
+                const int t = t0 + 4 * grp + s;
+                b4[s] = (t < H && col < m) ? rho[b] * basis[((size_t)b * H + t) * m + col] : 0.0f;
+              }
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-              const int o = (d * NR + 16 * rr + col) * 16 + 4 * grp;
-              *reinterpret_cast<f4*>(Xt + o) = Y[rr][0][d];
-              *reinterpret_cast<f4*>(Ct + o) = f4{0.0f, 0.0f, 0.0f, 0.0f};
+              for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+#pragma unroll
+                  for (int s = 0; s < 4; ++s) gacc[rr][d] = mfma4(Y[rr][d][s], b4[s], gacc[rr][d]);
             }
+          }
           wave_sync();
+          // ---- S2: broad phase over the tile, narrow phase on the surviving pairs ----
           for (int q2 = lane; q2 < n * 3; q2 += 64) {
             const int i = q2 / 3, d = q2 - 3 * (q2 / 3);
             const float* xr = Xt + (d * NR + i) * 16;
@@ -312,11 +334,11 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
           }
           wave_sync();
           int count = 0;
-          for (int base = 0; base < Np; base += 64) {
-            const int p = base + lane;
+#pragma unroll
+          for (int r = 0; r < PR; ++r) {
+            const int pij = mypair[r];
             bool act = false;
-            if (p < Np) {
-              const int pij = spairs[p];
+            if (pij >= 0) {
               const int i = pij & 255, j = pij >> 8;
               float g2 = 0.0f;
 #pragma unroll
@@ -327,7 +349,7 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
               act = g2 < 1.0001f;
             }
             const uint64_t mask = ballot(act);
-            if (act) plist[count + lanes_below(mask)] = p;
+            if (act) plist[count + lanes_below(mask)] = pij;
             count += __popcll(mask);
           }
           wave_sync();
@@ -335,7 +357,7 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
           for (int base = 0; base < count; base += 4) {
             const int slot = base + grp;
             if (slot < count && col < nt) {
-              const int pij = spairs[plist[slot]];
+              const int pij = plist[slot];
               const int i = pij & 255, j = pij >> 8;
               const float rx = Xt[(0 * NR + i) * 16 + col] - Xt[(0 * NR + j) * 16 + col];
               const float ry = Xt[(1 * NR + i) * 16 + col] - Xt[(1 * NR + j) * 16 + col];
@@ -353,34 +375,22 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
               }
             }
           }
-          nzc = ballot(nzc) != 0;
-          wave_sync();
-          // ---- S4 ----
-          if (nzc) {
+          if (ballot(nzc) != 0) {
+            wave_sync();
+            float b4[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              const int t = t0 + 4 * grp + s;
+              b4[s] = (t < H && col < m) ? rho[0] * basis[(size_t)t * m + col] : 0.0f;
+            }
 #pragma unroll
             for (int rr = 0; rr < R; ++rr)
 #pragma unroll
               for (int d = 0; d < 3; ++d) {
                 const f4 cr = *reinterpret_cast<const f4*>(Ct + (d * NR + 16 * rr + col) * 16 + 4 * grp);
 #pragma unroll
-                for (int s = 0; s < 4; ++s) gacc[rr][d] = mfma4(cr[s], b4[q][0][s], gacc[rr][d]);
+                for (int s = 0; s < 4; ++s) gacc[rr][d] = mfma4(cr[s], b4[s], gacc[rr][d]);
               }
-          }
-          if (nzv) {
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-              for (int d = 0; d < 3; ++d)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) gacc[rr][d] = mfma4(Y[rr][1][d][s], b4[q][1][s], gacc[rr][d]);
-          }
-          if (nza) {
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-              for (int d = 0; d < 3; ++d)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) gacc[rr][d] = mfma4(Y[rr][2][d][s], b4[q][2][s], gacc[rr][d]);
           }
           wave_sync();
         }
