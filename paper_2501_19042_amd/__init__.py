@@ -3,5 +3,5 @@
 The solver runs in the HIP kernels of libswarmsf.so (C ABI in include/swarmsf.h);
 this package marshals PyTorch device buffers and streams into that ABI.
 """
-from .sf import Batch, ProjectResult, SafetyFilter, factor_table  # noqa: F401
+from .sf import Batch, ProjectResult, SafetyFilter, factor_table, project_differentiable  # noqa: F401
 from . import _native  # noqa: F401

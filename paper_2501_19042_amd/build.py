@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libswarmsf.so")
-SOURCES = ["sf_api.hip", "sf_generic.hip", "sf_fast.hip"]
+SOURCES = ["sf_api.hip", "sf_generic.hip", "sf_fast.hip", "sf_adjoint.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

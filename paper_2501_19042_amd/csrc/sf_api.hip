@@ -3,6 +3,7 @@
 #include "swarmsf.h"
 #include "sf_internal.h"
 #include "sf_fast.h"
+#include "sf_adjoint.h"
 
 #include <algorithm>
 #include <cmath>
@@ -193,6 +194,8 @@ struct Plan {
 
 struct sf_handle_s {
   int device = 0;
+  void* scratch = nullptr;       // adjoint recompute states, grown on demand
+  size_t scratch_bytes = 0;
   std::vector<HostCfg> cfgs;
   sf::DevCfg* d_cfgs = nullptr;
   double* d_tab64 = nullptr;
@@ -306,6 +309,7 @@ sf_status pick_tile(sf_handle h, const Plan* p, size_t elem, size_t (*bytes)(con
 
 size_t generic_bytes(const sf::DevCfg& c, int tile, size_t elem) { return sf::generic_lds_bytes(c, tile, elem); }
 size_t feas_bytes(const sf::DevCfg& c, int tile, size_t) { return sf::feasibility_lds_bytes(c, tile); }
+size_t adj_bytes(const sf::DevCfg& c, int tile, size_t elem) { return sf::adjoint_lds_bytes(c, tile, elem); }
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
@@ -395,6 +399,7 @@ void sf_destroy(sf_handle h) {
   if (h->d_cfgs) (void)hipFree(h->d_cfgs);
   if (h->d_tab64) (void)hipFree(h->d_tab64);
   if (h->d_tab32) (void)hipFree(h->d_tab32);
+  if (h->scratch) (void)hipFree(h->scratch);
   delete h;
 }
 
@@ -458,10 +463,60 @@ sf_status sf_project_backward(sf_handle h, const sf_batch* batch, int32_t precis
                               const void* g_xi_out, const void* g_lam_out, const void* g_resid,
                               void* g_xi0, void* g_lam0, void* g_xi_bar, void* stream) {
   g_err.clear();
-  (void)h; (void)batch; (void)precision; (void)xi_bar; (void)bvals; (void)iters; (void)ckpt;
-  (void)ckpt_every; (void)g_xi_out; (void)g_lam_out; (void)g_resid; (void)g_xi0; (void)g_lam0;
-  (void)g_xi_bar; (void)stream;
-  return fail(SF_EUNSUPPORTED, "sf_project_backward is not available yet");
+  if (!h) return fail(SF_EINVAL, "handle is NULL");
+  if (precision < SF_FP64 || precision > SF_FP16) return fail(SF_EINVAL, "unknown precision");
+  if (!xi_bar || !bvals || !ckpt) return fail(SF_EINVAL, "xi_bar, bvals and ckpt are required");
+  if (iters < 0 || ckpt_every < 1) return fail(SF_EINVAL, "iters must be >= 0 and ckpt_every >= 1");
+  const size_t elem = precision == SF_FP64 ? sizeof(double) : sizeof(float);
+  const void* ptrs[] = {xi_bar, bvals, ckpt, g_xi_out, g_lam_out, g_resid, g_xi0, g_lam0, g_xi_bar};
+  for (const void* q : ptrs)
+    if (q && !aligned(q, elem)) return fail(SF_EINVAL, "misaligned array");
+  std::lock_guard<std::mutex> lock(h->mu);
+  sf_status st = check_device(h);
+  if (st != SF_OK) return st;
+  Plan* p = nullptr;
+  st = get_plan(h, batch, &p);
+  if (st != SF_OK) return st;
+  int64_t max_ndm = 0;
+  for (int32_t s : p->slots_used) {
+    const sf::DevCfg& c = h->cfgs[s].dev;
+    max_ndm = std::max<int64_t>(max_ndm, (int64_t)c.n * c.D * c.m);
+  }
+  sf::AdjointArgs a{};
+  a.state_stride = (int64_t)(ckpt_every + 1) * max_ndm;
+  const size_t need = (size_t)p->n_items * a.state_stride * elem;
+  if (need > h->scratch_bytes) {
+    if (h->scratch) (void)hipFree(h->scratch);
+    h->scratch = nullptr;
+    h->scratch_bytes = 0;
+    hipError_t e = hipMalloc(&h->scratch, need);
+    if (e != hipSuccess) return fail(SF_ENOMEM, "adjoint scratch allocation failed");
+    h->scratch_bytes = need;
+  }
+  a.cfgs = h->d_cfgs;
+  a.probs = p->d_probs;
+  a.items = p->d_items;
+  a.n_items = p->n_items;
+  a.xi_bar = xi_bar; a.bvals = bvals; a.iters = iters; a.ckpt = ckpt; a.ckpt_every = ckpt_every;
+  a.ckpt_stride = p->total_coef;
+  a.g_xi_out = g_xi_out; a.g_lam_out = g_lam_out; a.g_resid = g_resid;
+  a.g_xi0 = g_xi0; a.g_lam0 = g_lam0; a.g_xi_bar = g_xi_bar;
+  a.states = h->scratch;
+  a.stream = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (precision == SF_FP64) {
+    a.tab = h->d_tab64;
+    st = pick_tile(h, p, sizeof(double), adj_bytes, &a.tile, &a.lds_bytes);
+    if (st != SF_OK) return st;
+    e = sf::launch_adjoint<double>(a);
+  } else {
+    a.tab = h->d_tab32;
+    st = pick_tile(h, p, sizeof(float), adj_bytes, &a.tile, &a.lds_bytes);
+    if (st != SF_OK) return st;
+    e = sf::launch_adjoint<float>(a);
+  }
+  if (e != hipSuccess) return hip_fail(e, "sf_project_backward launch");
+  return SF_OK;
 }
 
 sf_status sf_feasibility(sf_handle h, const sf_batch* batch, int32_t precision, const void* xi,

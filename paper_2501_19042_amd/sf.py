@@ -171,3 +171,38 @@ def factor_table(cfg):
         "Rfx": t[offs[5]:offs[5] + 6 * mf].reshape(mf, 6),
         "m": m, "mf": mf, "H": H, "n": n,
     }
+
+
+class _SFProject(torch.autograd.Function):
+    """sf_project in the forward pass, sf_project_backward (hand-written adjoint through the
+    unrolled iterations, with checkpoints) in the backward pass."""
+
+    @staticmethod
+    def forward(ctx, xi0, lam0, xi_bar, bvals, sf, batch, iters, ckpt_every, precision):
+        out = sf.project(xi_bar.detach(), bvals.detach(), iters, batch=batch, precision=precision,
+                         xi0=xi0.detach(), lam0=lam0.detach(), ckpt_every=ckpt_every, generic=True)
+        ctx.save_for_backward(xi_bar.detach(), bvals.detach(), out.ckpt)
+        ctx.cfg = (sf, batch, iters, ckpt_every, precision)
+        return out.xi, out.lam, out.resid[:, 0].contiguous()
+
+    @staticmethod
+    def backward(ctx, g_xi, g_lam, g_res):
+        xi_bar, bvals, ckpt = ctx.saved_tensors
+        sf, batch, iters, ckpt_every, precision = ctx.cfg
+        c = lambda t: None if t is None else t.contiguous()
+        g = sf.project_backward(xi_bar, bvals, iters, ckpt, ckpt_every, g_xi_out=c(g_xi), g_lam_out=c(g_lam),
+                                g_resid=c(g_res), batch=batch, precision=precision)
+        return g["xi0"], g["lam0"], g["xi_bar"], None, None, None, None, None, None
+
+
+def project_differentiable(sf: SafetyFilter, xi_bar: torch.Tensor, bvals: torch.Tensor, iters: int,
+                           xi0: Optional[torch.Tensor] = None, lam0: Optional[torch.Tensor] = None,
+                           ckpt_every: int = 10, batch: Optional[Batch] = None, precision: str = "fp32"):
+    """Differentiable SF: returns (xi_K, lambda_K, ||r_p^K||^2 per sample); gradients flow to
+    xi0, lam0 and xi_bar through the adjoint kernel.  xi0 = None starts from xi_bar (its
+    gradient then adds to xi_bar's), lam0 = None starts from zero."""
+    if xi0 is None:
+        xi0 = xi_bar
+    if lam0 is None:
+        lam0 = torch.zeros_like(xi_bar)
+    return _SFProject.apply(xi0, lam0, xi_bar, bvals, sf, batch, int(iters), int(ckpt_every), precision)
