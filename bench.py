@@ -63,7 +63,19 @@ def main():
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--cpu-samples", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--generic", action="store_true", help="force the generic (non-MFMA) kernel")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 3 device copies of 256 MiB (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_copy": src.numel() * 4}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus above 1 is not supported "
                                    "(samples shard across GPUs without communication, see the design notes)"}))
@@ -85,7 +97,7 @@ def main():
     K = wl.iters
 
     for _ in range(args.warmup):
-        out = sf.project(xb, bv, K, precision=prec)
+        out = sf.project(xb, bv, K, precision=prec, generic=args.generic)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -93,7 +105,7 @@ def main():
     torch.cuda.synchronize()
     ev0.record(stream)
     for _ in range(args.steps):
-        out = sf.project(xb, bv, K, precision=prec)
+        out = sf.project(xb, bv, K, precision=prec, generic=args.generic)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
@@ -121,7 +133,8 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16+f32", "fp16": "f16+f32"}[prec],
         "data": "synthetic (seeded straight-line Bernstein fits + Gaussian coefficient noise)",
         "config": {"workload": wl.name, "samples": S, "robots": p.cfg.n_robots, "dims": p.cfg.dims,
-                   "degree": p.cfg.degree, "horizon": p.cfg.horizon, "iters": K, "precision": prec},
+                   "degree": p.cfg.degree, "horizon": p.cfg.horizon, "iters": K, "precision": prec,
+                   "kernel": "generic" if args.generic else "mfma"},
         "converged_fraction": n_conv / S,
         "all_samples_per_s": round(S / (ms / 1e3), 1),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",

@@ -48,7 +48,9 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
 }
 
 // LDS plan (in 4-byte words).  Per-wave tile buffers: positions Xt and collision residual
-// accumulator Ct as [axis][robot (16R)][time (16)], boxes bb [robot][6], active list.
+// accumulator Ct as [axis][robot (16R)][time], rows padded to kRS words so that the 16-byte
+// accesses of 8 consecutive lanes fall in distinct banks; boxes bb [robot][8]; active list.
+constexpr int kRS = 20;
 struct FastLds {
   int xi, lam, xb, xprev, gpart, xp, dlt, dbar, corr, ybuf, ybar, pairs, red, tiles, per_wave, total;
   int xt, ct, bb, plist;   // offsets inside one wave's tile region
@@ -73,9 +75,9 @@ __host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W) 
   p.red = o; o += 2 * 64 * W;
   o = (o + 3) & ~3;                       // 16-byte alignment of the tile buffers
   p.xt = 0;
-  p.ct = 3 * nr * 16;
-  p.bb = 6 * nr * 16;
-  p.plist = p.bb + 6 * nr;
+  p.ct = 3 * nr * kRS;
+  p.bb = 6 * nr * kRS;
+  p.plist = p.bb + 8 * nr;
   p.per_wave = (p.plist + Npmax + 3) & ~3;
   p.tiles = o;
   const int tiles_words = W * p.per_wave;
@@ -254,7 +256,7 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
           if (tau >= NT) break;
           const int t0 = 16 * tau;
           const int nt = min(16, H - t0);
-          // ---- S1 positions -> LDS ----
+          // ---- S1 positions -> LDS, per-robot boxes over the tile in registers ----
           {
             f4 Y[R][3];
 #pragma unroll
@@ -270,10 +272,34 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
             for (int rr = 0; rr < R; ++rr)
 #pragma unroll
               for (int d = 0; d < 3; ++d) {
-                const int o = (d * NR + 16 * rr + col) * 16 + 4 * grp;
+                const int o = (d * NR + 16 * rr + col) * kRS + 4 * grp;
                 *reinterpret_cast<f4*>(Xt + o) = Y[rr][d];
                 *reinterpret_cast<f4*>(Ct + o) = f4{0.0f, 0.0f, 0.0f, 0.0f};
               }
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+              float lo[3], hi[3];
+#pragma unroll
+              for (int d = 0; d < 3; ++d) {
+                lo[d] = FLT_MAX;
+                hi[d] = -FLT_MAX;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                  if (4 * grp + r < nt) {
+                    lo[d] = fminf(lo[d], Y[rr][d][r]);
+                    hi[d] = fmaxf(hi[d], Y[rr][d][r]);
+                  }
+                lo[d] = fminf(lo[d], __shfl_xor(lo[d], 16));
+                hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], 16));
+                lo[d] = fminf(lo[d], __shfl_xor(lo[d], 32));
+                hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], 32));
+              }
+              if (grp == 0) {
+                float* bq = bb + (16 * rr + col) * 8;
+                *reinterpret_cast<f4*>(bq) = f4{lo[0], lo[1], lo[2], 0.0f};
+                *reinterpret_cast<f4*>(bq + 4) = f4{hi[0], hi[1], hi[2], 0.0f};
+              }
+            }
           }
           // ---- S1 velocity / acceleration, S3 bound balls in registers, S4 for nonzero tiles ----
 #pragma unroll
@@ -321,18 +347,6 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
           }
           wave_sync();
           // ---- S2: broad phase over the tile, narrow phase on the surviving pairs ----
-          for (int q2 = lane; q2 < n * 3; q2 += 64) {
-            const int i = q2 / 3, d = q2 - 3 * (q2 / 3);
-            const float* xr = Xt + (d * NR + i) * 16;
-            float lo = xr[0], hi = xr[0];
-            for (int t = 1; t < nt; ++t) {
-              lo = fminf(lo, xr[t]);
-              hi = fmaxf(hi, xr[t]);
-            }
-            bb[i * 6 + d] = lo;
-            bb[i * 6 + 3 + d] = hi;
-          }
-          wave_sync();
           int count = 0;
 #pragma unroll
           for (int r = 0; r < PR; ++r) {
@@ -343,7 +357,7 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
               float g2 = 0.0f;
 #pragma unroll
               for (int d = 0; d < 3; ++d) {
-                const float gap = fmaxf(0.0f, fmaxf(bb[j * 6 + d] - bb[i * 6 + 3 + d], bb[i * 6 + d] - bb[j * 6 + 3 + d]));
+                const float gap = fmaxf(0.0f, fmaxf(bb[j * 8 + d] - bb[i * 8 + 4 + d], bb[i * 8 + d] - bb[j * 8 + 4 + d]));
                 g2 += gap * gap * (d == 2 ? ib2 : ia2);
               }
               act = g2 < 1.0001f;
@@ -359,19 +373,19 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
             if (slot < count && col < nt) {
               const int pij = plist[slot];
               const int i = pij & 255, j = pij >> 8;
-              const float rx = Xt[(0 * NR + i) * 16 + col] - Xt[(0 * NR + j) * 16 + col];
-              const float ry = Xt[(1 * NR + i) * 16 + col] - Xt[(1 * NR + j) * 16 + col];
-              const float rz = Xt[(2 * NR + i) * 16 + col] - Xt[(2 * NR + j) * 16 + col];
+              const float rx = Xt[(0 * NR + i) * kRS + col] - Xt[(0 * NR + j) * kRS + col];
+              const float ry = Xt[(1 * NR + i) * kRS + col] - Xt[(1 * NR + j) * kRS + col];
+              const float rz = Xt[(2 * NR + i) * kRS + col] - Xt[(2 * NR + j) * kRS + col];
               float Rx, Ry, Rz;
               coll_resid3(rx, ry, rz, ia2, ib2, sb, Rx, Ry, Rz);
               if (Rx != 0.0f || Ry != 0.0f || Rz != 0.0f) {
                 nzc = true;
-                atomicAdd(Ct + (0 * NR + i) * 16 + col, Rx);
-                atomicAdd(Ct + (1 * NR + i) * 16 + col, Ry);
-                atomicAdd(Ct + (2 * NR + i) * 16 + col, Rz);
-                atomicAdd(Ct + (0 * NR + j) * 16 + col, -Rx);
-                atomicAdd(Ct + (1 * NR + j) * 16 + col, -Ry);
-                atomicAdd(Ct + (2 * NR + j) * 16 + col, -Rz);
+                atomicAdd(Ct + (0 * NR + i) * kRS + col, Rx);
+                atomicAdd(Ct + (1 * NR + i) * kRS + col, Ry);
+                atomicAdd(Ct + (2 * NR + i) * kRS + col, Rz);
+                atomicAdd(Ct + (0 * NR + j) * kRS + col, -Rx);
+                atomicAdd(Ct + (1 * NR + j) * kRS + col, -Ry);
+                atomicAdd(Ct + (2 * NR + j) * kRS + col, -Rz);
               }
             }
           }
@@ -387,7 +401,7 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
             for (int rr = 0; rr < R; ++rr)
 #pragma unroll
               for (int d = 0; d < 3; ++d) {
-                const f4 cr = *reinterpret_cast<const f4*>(Ct + (d * NR + 16 * rr + col) * 16 + 4 * grp);
+                const f4 cr = *reinterpret_cast<const f4*>(Ct + (d * NR + 16 * rr + col) * kRS + 4 * grp);
 #pragma unroll
                 for (int s = 0; s < 4; ++s) gacc[rr][d] = mfma4(cr[s], b4[s], gacc[rr][d]);
               }
@@ -493,7 +507,7 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
                 for (int rr = 0; rr < R; ++rr)
 #pragma unroll
                   for (int d = 0; d < 3; ++d) {
-                    const int o = (d * NR + 16 * rr + col) * 16 + 4 * grp;
+                    const int o = (d * NR + 16 * rr + col) * kRS + 4 * grp;
                     *reinterpret_cast<f4*>(Xt + o) = Yp[rr][d];
                     *reinterpret_cast<f4*>(Ct + o) = Yn[rr][d];
                   }
@@ -527,8 +541,8 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
                 float rp[3], rn[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                  rp[d] = Xt[(d * NR + i) * 16 + col] - Xt[(d * NR + j) * 16 + col];
-                  rn[d] = Ct[(d * NR + i) * 16 + col] - Ct[(d * NR + j) * 16 + col];
+                  rp[d] = Xt[(d * NR + i) * kRS + col] - Xt[(d * NR + j) * kRS + col];
+                  rn[d] = Ct[(d * NR + i) * kRS + col] - Ct[(d * NR + j) * kRS + col];
                 }
                 float Rx, Ry, Rz;
                 coll_resid3(rp[0], rp[1], rp[2], ia2, ib2, sb, Rx, Ry, Rz);
