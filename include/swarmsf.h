@@ -56,6 +56,13 @@ typedef enum {
 /* Flags for sf_project. */
 #define SF_RESID_HISTORY 1   /* resid_out holds every iteration: [S][iters][2] */
 #define SF_GENERIC_KERNEL 2  /* use the generic LDS kernel even where the MFMA kernel applies */
+#define SF_USE_GRAPH 4       /* capture the launch sequence in a hipGraph on first use (per plan and
+                                argument set) and replay it; the first call must not be under capture */
+#define SF_AUTOTUNE 8        /* time the persistent launch's candidate grid sizes on this batch (on the
+                                first call; synchronizes) and keep the fastest, also in the JSON-lines
+                                cache $SWARMSF_TUNE_CACHE (default ~/.cache/swarmsf_tune.jsonl) */
+#define SF_PERSISTENT 16     /* run a single-shape batch through the persistent work-queue kernel (a
+                                batch of mixed swarm sizes always uses it on the MFMA path) */
 
 /* One problem shape (eqs. poly, inter_robot_con; bounds per the design notes).
  *  n_robots >= 2, dims in {2, 3}, degree >= 5 (Bernstein), horizon >= degree + 1,

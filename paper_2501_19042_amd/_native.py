@@ -9,6 +9,9 @@ SF_OK, SF_EINVAL, SF_ENOMEM, SF_EDEVICE, SF_EUNSUPPORTED = range(5)
 SF_FP64, SF_FP32, SF_BF16, SF_FP16 = range(4)
 SF_RESID_HISTORY = 1
 SF_GENERIC_KERNEL = 2
+SF_USE_GRAPH = 4
+SF_AUTOTUNE = 8
+SF_PERSISTENT = 16
 PRECISIONS = {"fp64": SF_FP64, "fp32": SF_FP32, "bf16": SF_BF16, "fp16": SF_FP16}
 
 EXPORTED = ["sf_setup", "sf_destroy", "sf_project", "sf_project_backward", "sf_feasibility",

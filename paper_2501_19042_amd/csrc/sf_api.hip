@@ -7,6 +7,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -187,7 +189,14 @@ struct Plan {
   int64_t total_samples = 0, total_coef = 0, total_bnd = 0;
   std::vector<sf::DevProblem> probs;
   std::vector<int32_t> slots_used;
+  std::vector<sf::WorkItem> items;      // host copy of the work items
   sf::FastPlan fast;            // MFMA-path plan (empty if not applicable)
+  sf::FastPlan fast_persistent; // persistent launch of a single-shape batch (built on request)
+  struct GraphEntry {
+    std::vector<uintptr_t> key;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<GraphEntry> graphs;       // captured launches, most recent first
 };
 
 }  // namespace
@@ -200,6 +209,8 @@ struct sf_handle_s {
   sf::DevCfg* d_cfgs = nullptr;
   double* d_tab64 = nullptr;
   float* d_tab32 = nullptr;
+  void* d_a16 = nullptr;         // 16-bit S1 basis operands of the MFMA kernels
+  hipStream_t cap_stream = nullptr;   // stream used to capture launch graphs
   std::vector<Plan*> plans;
   std::mutex mu;
 };
@@ -208,9 +219,12 @@ namespace {
 
 void free_plan(Plan* p) {
   if (!p) return;
+  for (auto& g : p->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (p->d_probs) (void)hipFree(p->d_probs);
   if (p->d_items) (void)hipFree(p->d_items);
   sf::fast_plan_free(p->fast);
+  sf::fast_plan_free(p->fast_persistent);
   delete p;
 }
 
@@ -276,7 +290,8 @@ sf_status get_plan(sf_handle h, const sf_batch* batch, Plan** out) {
   }
   std::vector<sf::DevCfg> cfgs;
   for (auto& hc : h->cfgs) cfgs.push_back(hc.dev);
-  sf_status st = sf::fast_plan_build(cfgs, p->probs, p->fast);
+  p->items = items;
+  sf_status st = sf::fast_plan_build(cfgs, p->probs, items, false, p->fast);
   if (st != SF_OK) {
     free_plan(p);
     return fail(st, "fast plan: " + sf::fast_last_error());
@@ -318,6 +333,107 @@ sf_status check_device(sf_handle h) {
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   if (dev != h->device) return fail(SF_EINVAL, "current device differs from the handle's device");
+  return SF_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Autotuner of the persistent launch: times candidate grid sizes on the caller's batch and
+// buffers, keeps the fastest per (device, batch, shapes, precision) in a JSON-lines cache.
+// ------------------------------------------------------------------------------------
+
+std::string tune_cache_path() {
+  if (const char* e = std::getenv("SWARMSF_TUNE_CACHE")) return e;
+  if (const char* home = std::getenv("HOME")) return std::string(home) + "/.cache/swarmsf_tune.jsonl";
+  return "";
+}
+
+std::string tune_signature(sf_handle h, const Plan* p, int precision) {
+  uint64_t f = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      f ^= (v >> (8 * i)) & 0xff;
+      f *= 1099511628211ull;
+    }
+  };
+  for (int32_t v : p->key) mix((uint64_t)(uint32_t)v);
+  for (int32_t s : p->slots_used) {
+    const sf::DevCfg& c = h->cfgs[s].dev;
+    mix(c.n); mix(c.m); mix(c.H); mix(c.D);
+  }
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) arch = prop.gcnArchName;
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "%s:p%d:%016llx", arch.c_str(), precision, (unsigned long long)f);
+  return buf;
+}
+
+int tune_lookup(const std::string& sig) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return 0;
+  FILE* fp = std::fopen(path.c_str(), "r");
+  if (!fp) return 0;
+  char line[512];
+  int found = 0;
+  while (std::fgets(line, sizeof(line), fp)) {
+    char key[256];
+    int grid = 0;
+    if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"grid\": %d", key, &grid) == 2 && sig == key) found = grid;
+  }
+  std::fclose(fp);
+  return found;
+}
+
+void tune_store(const std::string& sig, int grid, double ms) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  FILE* fp = std::fopen(path.c_str(), "a");
+  if (!fp) return;
+  std::fprintf(fp, "{\"key\": \"%s\", \"grid\": %d, \"ms\": %.4f}\n", sig.c_str(), grid, ms);
+  std::fclose(fp);
+}
+
+sf_status autotune(sf_handle h, const Plan* p, sf::FastPlan& fp, const sf::LaunchArgs& a, int precision) {
+  if (fp.tuned_grid[precision & 3] > 0) return SF_OK;
+  const std::string sig = tune_signature(h, p, precision);
+  const int cached = tune_lookup(sig);
+  if (cached > 0) {
+    fp.tuned_grid[precision & 3] = cached;
+    return SF_OK;
+  }
+  std::vector<int> cand;
+  for (int k = 1; k <= 4; ++k) cand.push_back(std::min(fp.ncu * k, p->n_items));
+  cand.push_back(p->n_items);
+  std::sort(cand.begin(), cand.end());
+  cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+  sf::LaunchArgs t = a;
+  t.iters = std::max(1, std::min(a.iters, 10));
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(SF_EDEVICE, "events");
+  int best = fp.grid;
+  float best_ms = 1e30f;
+  for (int g : cand) {
+    hipError_t e = sf::fast_launch_batched(fp, t, h->d_tab32, h->d_a16, precision, g);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, a.stream);
+    if (e == hipSuccess) e = sf::fast_launch_batched(fp, t, h->d_tab32, h->d_a16, precision, g);
+    if (e == hipSuccess) e = hipEventRecord(e1, a.stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return hip_fail(e, "autotune");
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = g;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  fp.tuned_grid[precision & 3] = best;
+  tune_store(sig, best, best_ms);
   return SF_OK;
 }
 
@@ -379,12 +495,38 @@ sf_status sf_setup(const sf_config* cfgs, int32_t n_cfgs, sf_handle* out) {
     h->cfgs.push_back(std::move(hc));
   }
   std::vector<float> all32(all.begin(), all.end());
+  // pre-split 16-bit basis operands (bf16 and fp16) of the MFMA kernels, 3D configs only
+  std::vector<uint16_t> a16;
+  for (size_t i = 0; i < devs.size(); ++i) {
+    sf::DevCfg& d = devs[i];
+    d.off_a16[0] = d.off_a16[1] = d.off_a32 = 0;
+    if (d.D != 3 || d.m > 16) continue;
+    {
+      const int64_t e32 = sf::a32_entries(d);
+      d.off_a32 = (int64_t)(a16.size() / 8);
+      a16.resize(a16.size() + e32 * 8);
+      sf::a32_fill(d, all.data() + d.off_basis, reinterpret_cast<float*>(a16.data() + d.off_a32 * 8));
+    }
+    const int64_t ent = sf::a16_entries(d);
+    for (int pr = 0; pr < 2; ++pr) {
+      d.off_a16[pr] = (int64_t)(a16.size() / 8);
+      a16.resize(a16.size() + ent * 8);
+      sf::a16_fill(d, all.data() + d.off_basis, pr == 0 ? SF_BF16 : SF_FP16,
+                   a16.data() + d.off_a16[pr] * 8);
+    }
+    h->cfgs[i].dev.off_a16[0] = d.off_a16[0];
+    h->cfgs[i].dev.off_a16[1] = d.off_a16[1];
+    h->cfgs[i].dev.off_a32 = d.off_a32;
+  }
+  if (a16.empty()) a16.resize(8);
   e = hipMalloc(&h->d_cfgs, devs.size() * sizeof(sf::DevCfg));
   if (e == hipSuccess) e = hipMalloc(&h->d_tab64, all.size() * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&h->d_tab32, all32.size() * sizeof(float));
   if (e == hipSuccess) e = hipMemcpy(h->d_cfgs, devs.data(), devs.size() * sizeof(sf::DevCfg), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(h->d_tab64, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(h->d_tab32, all32.data(), all32.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&h->d_a16, a16.size() * sizeof(uint16_t));
+  if (e == hipSuccess) e = hipMemcpy(h->d_a16, a16.data(), a16.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     sf_destroy(h);
     return hip_fail(e, "sf_setup upload");
@@ -399,6 +541,8 @@ void sf_destroy(sf_handle h) {
   if (h->d_cfgs) (void)hipFree(h->d_cfgs);
   if (h->d_tab64) (void)hipFree(h->d_tab64);
   if (h->d_tab32) (void)hipFree(h->d_tab32);
+  if (h->d_a16) (void)hipFree(h->d_a16);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->scratch) (void)hipFree(h->scratch);
   delete h;
 }
@@ -412,7 +556,8 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
   if (precision < SF_FP64 || precision > SF_FP16) return fail(SF_EINVAL, "unknown precision");
   if (!xi_bar || !bvals || !xi_out) return fail(SF_EINVAL, "xi_bar, bvals and xi_out are required");
   if (iters < 0) return fail(SF_EINVAL, "iters must be >= 0");
-  if (flags & ~(SF_RESID_HISTORY | SF_GENERIC_KERNEL)) return fail(SF_EINVAL, "unknown flags");
+  const int32_t known = SF_RESID_HISTORY | SF_GENERIC_KERNEL | SF_USE_GRAPH | SF_AUTOTUNE | SF_PERSISTENT;
+  if (flags & ~known) return fail(SF_EINVAL, "unknown flags");
   if (ckpt && ckpt_every < 1) return fail(SF_EINVAL, "ckpt_every must be >= 1 with a checkpoint buffer");
   const size_t elem = precision == SF_FP64 ? sizeof(double) : sizeof(float);
   const void* ptrs[] = {xi_bar, bvals, xi0, lam0, xi_out, lam_out, resid_out, ckpt};
@@ -424,7 +569,6 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
   Plan* p = nullptr;
   st = get_plan(h, batch, &p);
   if (st != SF_OK) return st;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   sf::LaunchArgs a{};
   a.cfgs = h->d_cfgs;
   a.probs = p->d_probs;
@@ -433,27 +577,82 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
   a.xi_bar = xi_bar; a.bvals = bvals; a.xi0 = xi0; a.lam0 = lam0; a.iters = iters;
   a.xi_out = xi_out; a.lam_out = lam_out; a.resid_out = resid_out; a.flags = flags & SF_RESID_HISTORY;
   a.ckpt = ckpt; a.ckpt_every = ckpt ? ckpt_every : 1; a.ckpt_stride = p->total_coef;
-  a.stream = s;
-  hipError_t e;
-  if (precision == SF_FP64) {
-    a.tab = h->d_tab64;
-    st = pick_tile(h, p, sizeof(double), generic_bytes, &a.tile, &a.lds_bytes);
-    if (st != SF_OK) return st;
-    e = sf::launch_generic_project<double>(a);
-  } else {
-    a.tab = h->d_tab32;
-    const bool want_fast = p->fast.ok && !(flags & (SF_RESID_HISTORY | SF_GENERIC_KERNEL));
-    if (precision != SF_FP32 && !want_fast)
-      return fail(SF_EUNSUPPORTED, "the MFMA precisions need a batch the MFMA kernels cover "
-                                   "(3D, supported swarm sizes) and no residual history");
-    if (want_fast) {
-      e = sf::fast_launch(p->fast, a, h->d_tab32, precision);
-    } else {
-      st = pick_tile(h, p, sizeof(float), generic_bytes, &a.tile, &a.lds_bytes);
-      if (st != SF_OK) return st;
-      e = sf::launch_generic_project<float>(a);
+  a.stream = static_cast<hipStream_t>(stream);
+
+  // choose the kernel path
+  sf::FastPlan* fp = nullptr;
+  if (precision != SF_FP64 && p->fast.ok && !(flags & (SF_RESID_HISTORY | SF_GENERIC_KERNEL))) {
+    fp = &p->fast;
+    if ((flags & SF_PERSISTENT) && !p->fast.batched) {
+      if (!p->fast_persistent.ok) {
+        std::vector<sf::DevCfg> cfgs;
+        for (auto& hc : h->cfgs) cfgs.push_back(hc.dev);
+        st = sf::fast_plan_build(cfgs, p->probs, p->items, true, p->fast_persistent);
+        if (st != SF_OK) return fail(st, "persistent plan: " + sf::fast_last_error());
+      }
+      if (p->fast_persistent.ok) fp = &p->fast_persistent;
     }
   }
+  if (precision > SF_FP32 && !fp)
+    return fail(SF_EUNSUPPORTED, "the MFMA precisions need a batch the MFMA kernels cover "
+                                 "(3D, up to 32 robots, degree <= 15, horizon <= 128) and no residual history");
+  if (!fp) {
+    st = pick_tile(h, p, elem, generic_bytes, &a.tile, &a.lds_bytes);
+    if (st != SF_OK) return st;
+  }
+  if (fp && fp->batched && (flags & SF_AUTOTUNE)) {
+    st = autotune(h, p, *fp, a, precision);
+    if (st != SF_OK) return st;
+  }
+  auto launch = [&](hipStream_t s) -> hipError_t {
+    sf::LaunchArgs b = a;
+    b.stream = s;
+    if (fp) return sf::fast_launch(*fp, b, h->d_tab32, h->d_a16, precision);
+    if (precision == SF_FP64) {
+      b.tab = h->d_tab64;
+      return sf::launch_generic_project<double>(b);
+    }
+    b.tab = h->d_tab32;
+    return sf::launch_generic_project<float>(b);
+  };
+  hipError_t e;
+  if (flags & SF_USE_GRAPH) {
+    std::vector<uintptr_t> key = {(uintptr_t)precision, (uintptr_t)flags, (uintptr_t)iters, (uintptr_t)a.ckpt_every,
+                                  (uintptr_t)fp, (uintptr_t)(fp ? fp->tuned_grid[precision & 3] : 0),
+                                  (uintptr_t)xi_bar, (uintptr_t)bvals, (uintptr_t)xi0, (uintptr_t)lam0,
+                                  (uintptr_t)xi_out, (uintptr_t)lam_out, (uintptr_t)resid_out, (uintptr_t)ckpt};
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : p->graphs)
+      if (g.key == key) exec = g.exec;
+    if (!exec) {
+      if (!h->cap_stream) {
+        e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "capture stream");
+      }
+      e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+      const hipError_t le = launch(h->cap_stream);
+      hipGraph_t graph = nullptr;
+      e = hipStreamEndCapture(h->cap_stream, &graph);
+      if (le != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(le, "sf_project launch (capture)");
+      }
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+      if (p->graphs.size() >= 4) {
+        (void)hipGraphExecDestroy(p->graphs.back().exec);
+        p->graphs.pop_back();
+      }
+      p->graphs.insert(p->graphs.begin(), Plan::GraphEntry{key, exec});
+    }
+    e = hipGraphLaunch(exec, a.stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return SF_OK;
+  }
+  e = launch(a.stream);
   if (e != hipSuccess) return hip_fail(e, "sf_project launch");
   return SF_OK;
 }

@@ -11,15 +11,33 @@ namespace sf {
 
 struct FastPlan {
   bool ok = false;              // the batch is covered by the fast kernels
-  int R = 0;                    // robot tiles of 16
-  int KS = 0;                   // k-steps of 4 coefficients
-  int TQ = 0;                   // time tiles per wave
+  int R = 0;                    // robot tiles of 16 (single-shape batches)
+  int KS = 0;                   // k-steps of 4 coefficients (maximum over the batch)
+  int TQ = 0;                   // time tiles per wave (maximum over the batch)
   size_t lds_bytes = 0;
+  // persistent launch over a ragged batch (mixed swarm sizes, or requested)
+  bool batched = false;
+  WorkItem* d_items_sorted = nullptr;   // work items, most expensive first
+  int* d_queue = nullptr;               // work-queue head, reset by a kernel before each launch
+  int ncu = 0;
+  int grid = 0;                         // default persistent workgroups
+  int tuned_grid[4] = {0, 0, 0, 0};     // autotuned persistent workgroups per precision (0 = not tuned)
 };
 
-sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<DevProblem>& probs, FastPlan& out);
+sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<DevProblem>& probs,
+                          const std::vector<WorkItem>& items, bool persistent, FastPlan& out);
 void fast_plan_free(FastPlan& p);
-hipError_t fast_launch(const FastPlan& p, const LaunchArgs& a, const float* tab32, int precision);
+hipError_t fast_launch(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16, int precision);
+hipError_t fast_launch_batched(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16,
+                               int precision, int grid);
+
+// Number of 16-byte entries of the 16-bit S1 basis-operand table of one config (per precision).
+int64_t a16_entries(const DevCfg& c);
+// Fill the table for one config: [tile][basis][instruction][lane] of 8 x 16-bit values.
+void a16_fill(const DevCfg& c, const double* P3, int precision, uint16_t* out);
+// fp32 S1 basis operands: [tile][basis][lane][4] floats (16-byte entries).
+int64_t a32_entries(const DevCfg& c);
+void a32_fill(const DevCfg& c, const double* P3, float* out);
 std::string fast_last_error();
 
 }  // namespace sf

@@ -19,6 +19,8 @@
 #include "sf_fast.h"
 
 #include <cfloat>
+#include <algorithm>
+#include <cstring>
 
 namespace sf {
 
@@ -32,6 +34,40 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// 16-bit operand types of v_mfma_f32_16x16x32_{bf16,f16}: MP = 1 bf16, MP = 2 fp16.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+template <int MP> struct Half;
+template <> struct Half<1> { typedef __bf16 E; typedef bf16x8 V; };
+template <> struct Half<2> { typedef _Float16 E; typedef f16x8 V; };
+
+__device__ __forceinline__ f4 mfma16(bf16x8 a, bf16x8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16(f16x8 a, f16x8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// B operands of the 16-bit S1 product for one robot tile and axis.  Lane (col, grp) covers
+// coefficients 8 (grp & 1) .. + 7 of robot col.  First instruction: grp 0, 1 carry xi_hi against
+// P_hi and grp 2, 3 carry xi_hi against P_lo; second instruction: grp 0, 1 carry xi_lo against
+// P_hi, grp 2, 3 are zero.  The sum is P_hi xi_hi + P_lo xi_hi + P_hi xi_lo in fp32: the
+// rounding residuals of both factors are fed back as correction terms.
+template <int MP>
+__device__ __forceinline__ void split_xi(const float* x, int robot, int n, int m, int d, int grp,
+                                         typename Half<MP>::V& b1, typename Half<MP>::V& b2) {
+  typedef typename Half<MP>::E E;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int k = 8 * (grp & 1) + v;
+    const float xv = (robot < n && k < m) ? x[(robot * 3 + d) * m + k] : 0.0f;
+    const E hi = static_cast<E>(xv);
+    const E lo = static_cast<E>(xv - static_cast<float>(hi));
+    b1[v] = hi;
+    b2[v] = grp < 2 ? lo : static_cast<E>(0.0f);
+  }
 }
 
 // Order LDS traffic between lanes of one wave (LDS instructions of a wave execute in order;
@@ -103,22 +139,51 @@ __device__ __forceinline__ void coll_resid3(float rx, float ry, float rz, float 
   }
 }
 
-template <int R, int KS, int W, int TQ>
-__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2, 2)))
-fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ tab,
-                    const DevProblem* __restrict__ probs, const WorkItem* __restrict__ items, int n_items,
-                    const float* __restrict__ xi_bar, const float* __restrict__ bvals,
-                    const float* __restrict__ xi0, const float* __restrict__ lam0, int iters,
-                    float* __restrict__ xi_out, float* __restrict__ lam_out, float* __restrict__ resid_out,
-                    float* __restrict__ ckpt, int ckpt_every, int64_t ckpt_stride) {
-  extern __shared__ __align__(16) float smem[];
+struct FastArgs {
+  const DevCfg* cfgs;
+  const float* tab;
+  const uint4* a16;
+  const DevProblem* probs;
+  const WorkItem* items;
+  int n_items;
+  const float* xi_bar;
+  const float* bvals;
+  const float* xi0;
+  const float* lam0;
+  int iters;
+  float* xi_out;
+  float* lam_out;
+  float* resid_out;
+  float* ckpt;
+  int ckpt_every;
+  int64_t ckpt_stride;
+};
+
+// The whole solve of one work item (its samples) by one workgroup.
+template <int R, int KS, int W, int TQ, int MP>
+__device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem) {
+  const DevCfg* __restrict__ cfgs = A.cfgs;
+  const float* __restrict__ tab = A.tab;
+  const uint4* __restrict__ a16 = A.a16;
+  const DevProblem* __restrict__ probs = A.probs;
+  const WorkItem* __restrict__ items = A.items;
+  const float* __restrict__ xi_bar = A.xi_bar;
+  const float* __restrict__ bvals = A.bvals;
+  const float* __restrict__ xi0 = A.xi0;
+  const float* __restrict__ lam0 = A.lam0;
+  const int iters = A.iters;
+  float* __restrict__ xi_out = A.xi_out;
+  float* __restrict__ lam_out = A.lam_out;
+  float* __restrict__ resid_out = A.resid_out;
+  float* __restrict__ ckpt = A.ckpt;
+  const int ckpt_every = A.ckpt_every;
+  const int64_t ckpt_stride = A.ckpt_stride;
   constexpr int NR = 16 * R;
   constexpr int PR = (NR * (NR - 1) / 2 + 63) / 64;   // 64-pair rounds of the broad phase
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, grp = lane >> 4;
   const int nthr = 64 * W;
-
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+  {
     const WorkItem w = items[it];
     const DevProblem pr = probs[w.problem];
     const DevCfg c = cfgs[pr.cfg];
@@ -162,21 +227,9 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
       for (int j = i + 1; j < n; ++j) spairs[p++] = i | (j << 8);
     }
     // loop-invariant MFMA A operands of this wave's tiles (basis rows of S1)
-    float a1[TQ][3][KS];
+    const float4* a32c = reinterpret_cast<const float4*>(a16) + c.off_a32;
     const float rho[3] = {(float)c.rho_c, (float)c.rho_v, (float)c.rho_a};
-#pragma unroll
-    for (int q = 0; q < TQ; ++q) {
-      const int t0 = 16 * (wave + W * q);
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          const int t = t0 + col, k = 4 * s + grp;
-          a1[q][b][s] = (t < H && k < m) ? basis[((size_t)b * H + t) * m + k] : 0.0f;
-        }
-      }
-    }
-
+    const uint4* a16c = a16 + (MP == 1 ? c.off_a16[0] : c.off_a16[1]);
     __syncthreads();
     int mypair[PR];
 #pragma unroll
@@ -234,23 +287,61 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
         if (resid_out && k == iters - 1)
           for (int q = tid; q < nDm; q += nthr) sxprev[q] = sxi[q];
         // S1 B operand: xi^T, lane (col, grp) holds robot col, coefficient 4 s + grp
-        float bx[R][3][KS];
+        float bx[MP == 0 ? R : 1][3][KS];
+        typename Half<MP == 0 ? 1 : MP>::V hb1[MP == 0 ? 1 : R][3], hb2[MP == 0 ? 1 : R][3];
+        if constexpr (MP == 0) {
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr)
+          for (int rr = 0; rr < R; ++rr)
 #pragma unroll
-          for (int d = 0; d < 3; ++d)
+            for (int d = 0; d < 3; ++d)
 #pragma unroll
-            for (int s = 0; s < KS; ++s) {
-              const int robot = 16 * rr + col, kk = 4 * s + grp;
-              bx[rr][d][s] = (robot < n && kk < m) ? sxi[(robot * 3 + d) * m + kk] : 0.0f;
-            }
+              for (int s = 0; s < KS; ++s) {
+                const int robot = 16 * rr + col, kk = 4 * s + grp;
+                bx[rr][d][s] = (robot < n && kk < m) ? sxi[(robot * 3 + d) * m + kk] : 0.0f;
+              }
+        } else {
+#pragma unroll
+          for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) split_xi<MP>(sxi, 16 * rr + col, n, m, d, grp, hb1[rr][d], hb2[rr][d]);
+        }
+        // S1 product for basis b of tile q: Y[rr][d] (lane (col, grp): robot col, times 4 grp + r)
+        auto s1 = [&](int q, int tau, int b, f4 (&Y)[R][3]) {
+          if constexpr (MP == 0) {
+            const float4 av = a32c[(tau * 3 + b) * 64 + lane];
+            const float a1[4] = {av.x, av.y, av.z, av.w};
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+              for (int d = 0; d < 3; ++d) {
+                f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int s = 0; s < KS; ++s) acc = mfma4(a1[s], bx[rr][d][s], acc);
+                Y[rr][d] = acc;
+              }
+          } else {
+            typedef typename Half<MP>::V V;
+            const uint4* at = a16c + ((tau * 3 + b) * 2) * 64 + lane;
+            const V A1 = __builtin_bit_cast(V, at[0]);
+            const V A2 = __builtin_bit_cast(V, at[64]);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+              for (int d = 0; d < 3; ++d) {
+                f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                acc = mfma16(A1, hb1[rr][d], acc);
+                acc = mfma16(A2, hb2[rr][d], acc);
+                Y[rr][d] = acc;
+              }
+          }
+        };
         f4 gacc[R][3];
 #pragma unroll
         for (int rr = 0; rr < R; ++rr)
 #pragma unroll
           for (int d = 0; d < 3; ++d) gacc[rr][d] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 
-#pragma unroll
+#pragma unroll 1
         for (int q = 0; q < TQ; ++q) {
           const int tau = wave + W * q;
           if (tau >= NT) break;
@@ -259,15 +350,7 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
           // ---- S1 positions -> LDS, per-robot boxes over the tile in registers ----
           {
             f4 Y[R][3];
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-              for (int d = 0; d < 3; ++d) {
-                f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                for (int s = 0; s < KS; ++s) acc = mfma4(a1[q][0][s], bx[rr][d][s], acc);
-                Y[rr][d] = acc;
-              }
+            s1(q, tau, 0, Y);
 #pragma unroll
             for (int rr = 0; rr < R; ++rr)
 #pragma unroll
@@ -308,15 +391,7 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
             if (!on) continue;
             const float lim = b == 1 ? vmax : amax;
             f4 Y[R][3];
-#pragma unroll
-            for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-              for (int d = 0; d < 3; ++d) {
-                f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                for (int s = 0; s < KS; ++s) acc = mfma4(a1[q][b][s], bx[rr][d][s], acc);
-                Y[rr][d] = acc;
-              }
+            s1(q, tau, b, Y);
             bool nz = false;
 #pragma unroll
             for (int rr = 0; rr < R; ++rr)
@@ -468,19 +543,31 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
       if (resid_out) {
         float ss = 0.0f, mx = 0.0f;
         if (iters > 0) {
-          float bp[R][3][KS], bn[R][3][KS];
+          float bp[MP == 0 ? R : 1][3][KS], bn[MP == 0 ? R : 1][3][KS];
+          typename Half<MP == 0 ? 1 : MP>::V pb1[MP == 0 ? 1 : R][3], pb2[MP == 0 ? 1 : R][3];
+          typename Half<MP == 0 ? 1 : MP>::V nb1[MP == 0 ? 1 : R][3], nb2[MP == 0 ? 1 : R][3];
+          if constexpr (MP == 0) {
 #pragma unroll
-          for (int rr = 0; rr < R; ++rr)
+            for (int rr = 0; rr < R; ++rr)
 #pragma unroll
-            for (int d = 0; d < 3; ++d)
+              for (int d = 0; d < 3; ++d)
 #pragma unroll
-              for (int s = 0; s < KS; ++s) {
-                const int robot = 16 * rr + col, kk = 4 * s + grp;
-                const bool ok = robot < n && kk < m;
-                bp[rr][d][s] = ok ? sxprev[(robot * 3 + d) * m + kk] : 0.0f;
-                bn[rr][d][s] = ok ? sxi[(robot * 3 + d) * m + kk] : 0.0f;
+                for (int s = 0; s < KS; ++s) {
+                  const int robot = 16 * rr + col, kk = 4 * s + grp;
+                  const bool ok = robot < n && kk < m;
+                  bp[rr][d][s] = ok ? sxprev[(robot * 3 + d) * m + kk] : 0.0f;
+                  bn[rr][d][s] = ok ? sxi[(robot * 3 + d) * m + kk] : 0.0f;
+                }
+          } else {
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+              for (int d = 0; d < 3; ++d) {
+                split_xi<MP>(sxprev, 16 * rr + col, n, m, d, grp, pb1[rr][d], pb2[rr][d]);
+                split_xi<MP>(sxi, 16 * rr + col, n, m, d, grp, nb1[rr][d], nb2[rr][d]);
               }
-#pragma unroll
+          }
+#pragma unroll 1
           for (int q = 0; q < TQ; ++q) {
             const int tau = wave + W * q;
             if (tau >= NT) break;
@@ -489,19 +576,40 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
               f4 Yp[R][3], Yn[R][3];
+              if constexpr (MP == 0) {
+                const float4 av = a32c[(tau * 3 + b) * 64 + lane];
+                const float a1[4] = {av.x, av.y, av.z, av.w};
 #pragma unroll
-              for (int rr = 0; rr < R; ++rr)
+                for (int rr = 0; rr < R; ++rr)
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                  f4 ap = {0.0f, 0.0f, 0.0f, 0.0f}, an = {0.0f, 0.0f, 0.0f, 0.0f};
+                  for (int d = 0; d < 3; ++d) {
+                    f4 ap = {0.0f, 0.0f, 0.0f, 0.0f}, an = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                  for (int s = 0; s < KS; ++s) {
-                    ap = mfma4(a1[q][b][s], bp[rr][d][s], ap);
-                    an = mfma4(a1[q][b][s], bn[rr][d][s], an);
+                    for (int s = 0; s < KS; ++s) {
+                      ap = mfma4(a1[s], bp[rr][d][s], ap);
+                      an = mfma4(a1[s], bn[rr][d][s], an);
+                    }
+                    Yp[rr][d] = ap;
+                    Yn[rr][d] = an;
                   }
-                  Yp[rr][d] = ap;
-                  Yn[rr][d] = an;
-                }
+              } else {
+                typedef typename Half<MP>::V V;
+                const uint4* at = a16c + ((tau * 3 + b) * 2) * 64 + lane;
+                const V A1 = __builtin_bit_cast(V, at[0]);
+                const V A2 = __builtin_bit_cast(V, at[64]);
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+                  for (int d = 0; d < 3; ++d) {
+                    f4 ap = {0.0f, 0.0f, 0.0f, 0.0f}, an = {0.0f, 0.0f, 0.0f, 0.0f};
+                    ap = mfma16(A1, pb1[rr][d], ap);
+                    ap = mfma16(A2, pb2[rr][d], ap);
+                    an = mfma16(A1, nb1[rr][d], an);
+                    an = mfma16(A2, nb2[rr][d], an);
+                    Yp[rr][d] = ap;
+                    Yn[rr][d] = an;
+                  }
+              }
               if (b == 0) {
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr)
@@ -578,65 +686,293 @@ fast_project_kernel(const DevCfg* __restrict__ cfgs, const float* __restrict__ t
   }
 }
 
+// One workgroup per work item (grid-stride), single shape class.
+template <int R, int KS, int W, int TQ, int MP, int WPE>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+fast_project_kernel(FastArgs A) {
+  extern __shared__ __align__(16) float smem[];
+  for (int it = blockIdx.x; it < A.n_items; it += gridDim.x) fast_item<R, KS, W, TQ, MP>(A, it, smem);
+}
+
+// Persistent kernel over a ragged batch: workgroups pull work items (sorted by decreasing cost
+// on the host) from an atomic queue until it is empty; each item runs the body for its swarm
+// size (up to 16 robots, or up to 32).  Every wave reaches the exit once the queue is drained.
+template <int KS, int W, int TQ, int MP, int WPE>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+fast_batched_kernel(FastArgs A, int* __restrict__ queue) {
+  extern __shared__ __align__(16) float smem[];
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+    __syncthreads();
+    const int it = next;
+    __syncthreads();
+    if (it >= A.n_items) break;
+    const int n = A.cfgs[A.probs[A.items[it].problem].cfg].n;
+    if (n <= 16) fast_item<1, KS, W, TQ, MP>(A, it, smem);
+    else fast_item<2, KS, W, TQ, MP>(A, it, smem);
+  }
+}
+
+__global__ void reset_queue_kernel(int* queue) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0;
+}
+
 // Kernel instances: R robot tiles of 16, KS k-steps of 4 coefficients, W waves, TQ tiles per wave.
 constexpr int kW = 4;
+// Target waves per SIMD: the register budget that fits each instance without spills.
+constexpr int waves_per_simd(int R, int MP) { return (R == 1 && MP == 0) ? 3 : (R == 1 ? 2 : (MP == 0 ? 2 : 1)); }
 
-template <int R, int KS, int TQ>
-hipError_t launch_instance(const FastPlan& p, const LaunchArgs& a, const float* tab32) {
-  auto kern = fast_project_kernel<R, KS, kW, TQ>;
+FastArgs make_fast_args(const LaunchArgs& a, const float* tab32, const uint4* a16) {
+  FastArgs f;
+  f.cfgs = a.cfgs; f.tab = tab32; f.a16 = a16; f.probs = a.probs; f.items = a.items; f.n_items = a.n_items;
+  f.xi_bar = static_cast<const float*>(a.xi_bar); f.bvals = static_cast<const float*>(a.bvals);
+  f.xi0 = static_cast<const float*>(a.xi0); f.lam0 = static_cast<const float*>(a.lam0); f.iters = a.iters;
+  f.xi_out = static_cast<float*>(a.xi_out); f.lam_out = static_cast<float*>(a.lam_out);
+  f.resid_out = static_cast<float*>(a.resid_out); f.ckpt = static_cast<float*>(a.ckpt);
+  f.ckpt_every = a.ckpt_every; f.ckpt_stride = a.ckpt_stride;
+  return f;
+}
+
+template <int R, int KS, int TQ, int MP>
+hipError_t launch_instance(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16) {
+  auto kern = fast_project_kernel<R, KS, kW, TQ, MP, waves_per_simd(R, MP)>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(a.n_items), dim3(64 * kW), p.lds_bytes, a.stream, a.cfgs, tab32, a.probs,
-                     a.items, a.n_items, static_cast<const float*>(a.xi_bar), static_cast<const float*>(a.bvals),
-                     static_cast<const float*>(a.xi0), static_cast<const float*>(a.lam0), a.iters,
-                     static_cast<float*>(a.xi_out), static_cast<float*>(a.lam_out),
-                     static_cast<float*>(a.resid_out), static_cast<float*>(a.ckpt), a.ckpt_every, a.ckpt_stride);
+  hipLaunchKernelGGL(kern, dim3(a.n_items), dim3(64 * kW), p.lds_bytes, a.stream, make_fast_args(a, tab32, a16));
   return hipGetLastError();
 }
 
 }  // namespace
 
-sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<DevProblem>& probs, FastPlan& out) {
+int64_t a16_entries(const DevCfg& c) { return (int64_t)((c.H + 15) / 16) * 3 * 2 * 64; }
+
+namespace {
+
+uint16_t bf16_bits(float f) {            // round to nearest even
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+float bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+uint16_t f16_bits(float f) {
+  const _Float16 h = static_cast<_Float16>(f);
+  uint16_t b;
+  std::memcpy(&b, &h, 2);
+  return b;
+}
+
+float f16_value(uint16_t b) {
+  _Float16 h;
+  std::memcpy(&h, &b, 2);
+  return static_cast<float>(h);
+}
+
+}  // namespace
+
+int64_t a32_entries(const DevCfg& c) { return (int64_t)((c.H + 15) / 16) * 3 * 64; }
+
+void a32_fill(const DevCfg& c, const double* P3, float* out) {
+  const int NT = (c.H + 15) / 16;
+  for (int tau = 0; tau < NT; ++tau)
+    for (int b = 0; b < 3; ++b)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int col = lane & 15, grp = lane >> 4, t = 16 * tau + col;
+        for (int s = 0; s < 4; ++s) {
+          const int k = 4 * s + grp;
+          out[(((size_t)tau * 3 + b) * 64 + lane) * 4 + s] =
+              (t < c.H && k < c.m) ? (float)P3[((size_t)b * c.H + t) * c.m + k] : 0.0f;
+        }
+      }
+}
+
+void a16_fill(const DevCfg& c, const double* P3, int precision, uint16_t* out) {
+  const int NT = (c.H + 15) / 16;
+  const bool bf = precision == SF_BF16;
+  for (int tau = 0; tau < NT; ++tau)
+    for (int b = 0; b < 3; ++b)
+      for (int inst = 0; inst < 2; ++inst)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int col = lane & 15, grp = lane >> 4, t = 16 * tau + col;
+          for (int v = 0; v < 8; ++v) {
+            const int k = 8 * (grp & 1) + v;
+            uint16_t bits = 0;
+            if (t < c.H && k < c.m) {
+              const double P = P3[((size_t)b * c.H + t) * c.m + k];
+              const uint16_t hi = bf ? bf16_bits((float)P) : f16_bits((float)P);
+              const double hv = bf ? bf16_value(hi) : f16_value(hi);
+              const uint16_t lo = bf ? bf16_bits((float)(P - hv)) : f16_bits((float)(P - hv));
+              if (grp < 2) bits = hi;
+              else bits = inst == 0 ? lo : 0;
+            }
+            out[((((size_t)tau * 3 + b) * 2 + inst) * 64 + lane) * 8 + v] = bits;
+          }
+        }
+}
+
+namespace {
+
+bool cfg_supported(const DevCfg& c) { return c.D == 3 && c.n <= 32 && c.m <= 16 && c.H <= 16 * kW * 2; }
+
+// Relative cost of one sample-iteration: S1 MFMA work grows with the robot tiles and time tiles,
+// the broad phase with the number of pairs.
+double item_cost(const DevCfg& c, int count) {
+  const int NT = (c.H + 15) / 16;
+  const int R = c.n <= 16 ? 1 : 2;
+  return (double)count * NT * (24.0 * R * ((c.m + 3) / 4) + c.n * (c.n - 1) / 2.0);
+}
+
+}  // namespace
+
+sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<DevProblem>& probs,
+                          const std::vector<WorkItem>& items, bool persistent, FastPlan& out) {
+  fast_plan_free(out);
   out = FastPlan();
   if (probs.empty()) return SF_OK;
-  const int slot = probs[0].cfg;
-  for (const DevProblem& p : probs)
-    if (p.cfg != slot) return SF_OK;          // mixed shapes: generic path
-  const DevCfg& c = cfgs[slot];
-  if (c.D != 3 || c.n > 32 || c.m > 16 || c.H > 16 * kW * 2 || c.n > 255) return SF_OK;
-  out.R = c.n <= 16 ? 1 : 2;
-  out.KS = (c.m + 3) / 4;
-  const int NT = (c.H + 15) / 16;
-  out.TQ = (NT + kW - 1) / kW;
-  if (out.KS < 2) out.KS = 2;
-  out.lds_bytes = (size_t)fast_lds_plan(c, out.R, kW).total * 4;
-  if (out.lds_bytes > 160 * 1024) return SF_OK;
+  bool mixed = false;
+  int maxKS = 2, maxNT = 1;
+  size_t lds = 0;
+  for (const DevProblem& p : probs) {
+    const DevCfg& c = cfgs[p.cfg];
+    if (!cfg_supported(c)) return SF_OK;                 // generic path
+    if (p.cfg != probs[0].cfg) mixed = true;
+    maxKS = std::max(maxKS, (c.m + 3) / 4);
+    maxNT = std::max(maxNT, (c.H + 15) / 16);
+    lds = std::max(lds, (size_t)fast_lds_plan(c, c.n <= 16 ? 1 : 2, kW).total * 4);
+  }
+  if (lds > 160 * 1024) return SF_OK;
+  const DevCfg& c0 = cfgs[probs[0].cfg];
+  out.KS = maxKS;
+  out.TQ = (maxNT + kW - 1) / kW;
+  out.R = c0.n <= 16 ? 1 : 2;
+  out.lds_bytes = lds;
+  out.batched = mixed || persistent;
+  if (out.batched) {
+    // longest-processing-time order: most expensive work items first
+    std::vector<std::pair<double, int>> order(items.size());
+    for (size_t i = 0; i < items.size(); ++i) {
+      const DevProblem& p = probs[items[i].problem];
+      order[i] = {item_cost(cfgs[p.cfg], items[i].count), (int)i};
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<double, int>& a, const std::pair<double, int>& b) { return a.first > b.first; });
+    std::vector<WorkItem> sorted(items.size());
+    for (size_t i = 0; i < items.size(); ++i) sorted[i] = items[order[i].second];
+    hipError_t e = hipMalloc(&out.d_items_sorted, sorted.size() * sizeof(WorkItem));
+    if (e == hipSuccess)
+      e = hipMemcpy(out.d_items_sorted, sorted.data(), sorted.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&out.d_queue, sizeof(int));
+    if (e != hipSuccess) {
+      fast_plan_free(out);
+      g_fast_err = "persistent plan allocation failed";
+      return SF_ENOMEM;
+    }
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    out.ncu = ncu > 0 ? ncu : 256;
+    const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(lds, 1))));
+    out.grid = std::min<int>((int)items.size(), out.ncu * per_cu);
+  }
   out.ok = true;
   return SF_OK;
 }
 
-void fast_plan_free(FastPlan& p) { p.ok = false; }
+void fast_plan_free(FastPlan& p) {
+  if (p.d_items_sorted) (void)hipFree(p.d_items_sorted);
+  if (p.d_queue) (void)hipFree(p.d_queue);
+  p.d_items_sorted = nullptr;
+  p.d_queue = nullptr;
+  p.ok = false;
+}
 
-hipError_t fast_launch(const FastPlan& p, const LaunchArgs& a, const float* tab32, int precision) {
-  if (precision != SF_FP32) {
-    g_fast_err = "precision not implemented in the MFMA kernels";
-    return hipErrorNotSupported;
+namespace {
+
+template <int KS, int TQ, int MP>
+hipError_t launch_batched(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16, int grid) {
+  auto kern = fast_batched_kernel<KS, kW, TQ, MP, waves_per_simd(2, MP)>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
+  if (e != hipSuccess) return e;
+  FastArgs f = make_fast_args(a, tab32, a16);
+  f.items = p.d_items_sorted;
+  hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, a.stream, p.d_queue);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kW), p.lds_bytes, a.stream, f, p.d_queue);
+  return hipGetLastError();
+}
+
+template <int MP>
+hipError_t launch_batched_mp(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16, int grid) {
+  const int key = p.KS * 10 + p.TQ;
+  switch (key) {
+    case 21: return launch_batched<2, 1, MP>(p, a, tab32, a16, grid);
+    case 22: return launch_batched<2, 2, MP>(p, a, tab32, a16, grid);
+    case 31: return launch_batched<3, 1, MP>(p, a, tab32, a16, grid);
+    case 32: return launch_batched<3, 2, MP>(p, a, tab32, a16, grid);
+    case 41: return launch_batched<4, 1, MP>(p, a, tab32, a16, grid);
+    case 42: return launch_batched<4, 2, MP>(p, a, tab32, a16, grid);
+    default:
+      g_fast_err = "no persistent kernel instance for this shape";
+      return hipErrorNotSupported;
   }
+}
+
+}  // namespace
+
+hipError_t fast_launch_batched(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16,
+                               int precision, int grid) {
+  const uint4* t = static_cast<const uint4*>(a16);
+  switch (precision) {
+    case SF_FP32: return launch_batched_mp<0>(p, a, tab32, t, grid);
+    case SF_BF16: return launch_batched_mp<1>(p, a, tab32, t, grid);
+    case SF_FP16: return launch_batched_mp<2>(p, a, tab32, t, grid);
+    default:
+      g_fast_err = "precision not implemented in the MFMA kernels";
+      return hipErrorNotSupported;
+  }
+}
+
+template <int MP>
+hipError_t launch_mp(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16) {
   const int key = p.R * 100 + p.KS * 10 + p.TQ;
   switch (key) {
-    case 121: return launch_instance<1, 2, 1>(p, a, tab32);
-    case 122: return launch_instance<1, 2, 2>(p, a, tab32);
-    case 131: return launch_instance<1, 3, 1>(p, a, tab32);
-    case 132: return launch_instance<1, 3, 2>(p, a, tab32);
-    case 141: return launch_instance<1, 4, 1>(p, a, tab32);
-    case 142: return launch_instance<1, 4, 2>(p, a, tab32);
-    case 231: return launch_instance<2, 3, 1>(p, a, tab32);
-    case 232: return launch_instance<2, 3, 2>(p, a, tab32);
-    case 241: return launch_instance<2, 4, 1>(p, a, tab32);
-    case 242: return launch_instance<2, 4, 2>(p, a, tab32);
+    case 121: return launch_instance<1, 2, 1, MP>(p, a, tab32, a16);
+    case 122: return launch_instance<1, 2, 2, MP>(p, a, tab32, a16);
+    case 131: return launch_instance<1, 3, 1, MP>(p, a, tab32, a16);
+    case 132: return launch_instance<1, 3, 2, MP>(p, a, tab32, a16);
+    case 141: return launch_instance<1, 4, 1, MP>(p, a, tab32, a16);
+    case 142: return launch_instance<1, 4, 2, MP>(p, a, tab32, a16);
+    case 231: return launch_instance<2, 3, 1, MP>(p, a, tab32, a16);
+    case 232: return launch_instance<2, 3, 2, MP>(p, a, tab32, a16);
+    case 241: return launch_instance<2, 4, 1, MP>(p, a, tab32, a16);
+    case 242: return launch_instance<2, 4, 2, MP>(p, a, tab32, a16);
     default:
       g_fast_err = "no kernel instance for this shape";
+      return hipErrorNotSupported;
+  }
+}
+
+hipError_t fast_launch(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16, int precision) {
+  if (p.batched) {
+    const int g = p.tuned_grid[precision & 3] > 0 ? p.tuned_grid[precision & 3] : p.grid;
+    return fast_launch_batched(p, a, tab32, a16, precision, g);
+  }
+  const uint4* t = static_cast<const uint4*>(a16);
+  switch (precision) {
+    case SF_FP32: return launch_mp<0>(p, a, tab32, t);
+    case SF_BF16: return launch_mp<1>(p, a, tab32, t);
+    case SF_FP16: return launch_mp<2>(p, a, tab32, t);
+    default:
+      g_fast_err = "precision not implemented in the MFMA kernels";
       return hipErrorNotSupported;
   }
 }

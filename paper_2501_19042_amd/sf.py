@@ -96,23 +96,29 @@ class SafetyFilter:
     def project(self, xi_bar: torch.Tensor, bvals: torch.Tensor, iters: int, batch: Optional[Batch] = None,
                 precision: str = "fp32", xi0: Optional[torch.Tensor] = None, lam0: Optional[torch.Tensor] = None,
                 want_lam: bool = True, want_resid: bool = True, history: bool = False,
-                ckpt_every: int = 0, generic: bool = False, stream=None) -> ProjectResult:
+                ckpt_every: int = 0, generic: bool = False, graph: bool = False, autotune: bool = False,
+                persistent: bool = False, out: Optional[ProjectResult] = None, stream=None) -> ProjectResult:
         prec = N.PRECISIONS[precision]
         dtype = torch.float64 if prec == N.SF_FP64 else torch.float32
         batch = self._batch(batch, xi_bar)
         S, coef, bnd = self.sizes(batch)
         for t, nm, ne in ((xi_bar, "xi_bar", coef), (bvals, "bvals", bnd), (xi0, "xi0", coef), (lam0, "lam0", coef)):
             self._check(t, nm, dtype, ne)
-        xi_out = torch.empty_like(xi_bar)
-        lam_out = torch.empty_like(xi_bar) if want_lam else None
-        resid = None
-        if want_resid:
-            resid = torch.empty((S, iters, 2) if history else (S, 2), dtype=dtype, device=self.device)
-        ckpt = None
-        if ckpt_every:
-            nck = max(1, math.ceil(iters / ckpt_every))
-            ckpt = torch.empty((nck, 2, coef), dtype=dtype, device=self.device)
-        flags = (N.SF_RESID_HISTORY if history else 0) | (N.SF_GENERIC_KERNEL if generic else 0)
+        if out is not None:           # caller-provided outputs (fixed addresses, e.g. for graph replay)
+            xi_out, lam_out, resid, ckpt = out
+        else:
+            xi_out = torch.empty_like(xi_bar)
+            lam_out = torch.empty_like(xi_bar) if want_lam else None
+            resid = None
+            if want_resid:
+                resid = torch.empty((S, iters, 2) if history else (S, 2), dtype=dtype, device=self.device)
+            ckpt = None
+            if ckpt_every:
+                nck = max(1, math.ceil(iters / ckpt_every))
+                ckpt = torch.empty((nck, 2, coef), dtype=dtype, device=self.device)
+        flags = ((N.SF_RESID_HISTORY if history else 0) | (N.SF_GENERIC_KERNEL if generic else 0)
+                 | (N.SF_USE_GRAPH if graph else 0) | (N.SF_AUTOTUNE if autotune else 0)
+                 | (N.SF_PERSISTENT if persistent else 0))
         N.check(N.lib().sf_project(self._h, ctypes.byref(batch.c), prec, _ptr(xi_bar), _ptr(bvals), _ptr(xi0),
                                    _ptr(lam0), int(iters), _ptr(xi_out), _ptr(lam_out), _ptr(resid), flags,
                                    _ptr(ckpt), int(ckpt_every), _stream_ptr(stream)))

@@ -1,0 +1,134 @@
+"""Batching form: uneven swarm sizes and sample counts in one persistent launch (work queue,
+longest items first), hipGraph capture/replay and the autotuner."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2501_19042_amd as P
+    torch.cuda.set_device(0)
+    return P
+
+
+def ragged_problems():
+    out = []
+    for k, (n, S) in enumerate([(8, 3), (16, 2), (32, 2), (8, 1), (12, 4), (20, 1)]):
+        out.append(W.small3d(n_robots=n, n_samples=S, degree=10, horizon=100, seed=300 + k,
+                             box=((-3.0, -3.0, -1.0), (3.0, 3.0, 1.0)), t_final=10.0))
+    return out
+
+
+def pack(problems):
+    xb = torch.cat([torch.tensor(p.xi_bar, dtype=torch.float32).reshape(-1) for p in problems]).cuda()
+    bv = torch.cat([torch.tensor(p.bvals, dtype=torch.float32).reshape(-1) for p in problems]).cuda()
+    return xb, bv
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_persistent_ragged_equals_per_problem_launches(P, prec):
+    probs = ragged_problems()
+    sf = P.SafetyFilter([p.cfg for p in probs])
+    batch = P.Batch([(i, p.xi_bar.shape[0]) for i, p in enumerate(probs)])
+    xb, bv = pack(probs)
+    out = sf.project(xb, bv, 40, batch=batch, precision=prec)
+    torch.cuda.synchronize()
+    o = r = 0
+    for i, p in enumerate(probs):
+        one = P.SafetyFilter([p.cfg])
+        single = one.project(torch.tensor(p.xi_bar, dtype=torch.float32).cuda(),
+                             torch.tensor(p.bvals, dtype=torch.float32).cuda(), 40, precision=prec)
+        torch.cuda.synchronize()
+        nel, S = p.xi_bar.size, p.xi_bar.shape[0]
+        assert torch.equal(out.xi[o:o + nel].cpu(), single.xi.reshape(-1).cpu()), i
+        assert torch.equal(out.lam[o:o + nel].cpu(), single.lam.reshape(-1).cpu()), i
+        assert torch.equal(out.resid[r:r + S].cpu(), single.resid.cpu()), i
+        o += nel
+        r += S
+
+
+def test_persistent_single_shape_equals_plain(P):
+    p = W.small3d(n_robots=16, n_samples=40, horizon=100, seed=5, box=((-3.0, -3.0, -1.0), (3.0, 3.0, 1.0)),
+                  t_final=10.0)
+    sf = P.SafetyFilter([p.cfg])
+    xb = torch.tensor(p.xi_bar, dtype=torch.float32).cuda()
+    bv = torch.tensor(p.bvals, dtype=torch.float32).cuda()
+    a = sf.project(xb, bv, 30, precision="fp32")
+    b = sf.project(xb, bv, 30, precision="fp32", persistent=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a.xi, b.xi) and torch.equal(a.lam, b.lam) and torch.equal(a.resid, b.resid)
+
+
+def test_graph_replay_matches_eager(P):
+    probs = ragged_problems()
+    sf = P.SafetyFilter([p.cfg for p in probs])
+    batch = P.Batch([(i, p.xi_bar.shape[0]) for i, p in enumerate(probs)])
+    xb, bv = pack(probs)
+    eager = sf.project(xb, bv, 25, batch=batch, precision="fp32")
+    torch.cuda.synchronize()
+    S = batch.n_samples
+    bufs = P.ProjectResult(torch.empty_like(xb), torch.empty_like(xb),
+                           torch.empty((S, 2), dtype=torch.float32, device="cuda"), None)
+    for rep in range(4):
+        bufs.xi.fill_(float("nan"))
+        bufs.lam.fill_(float("nan"))
+        bufs.resid.fill_(float("nan"))
+        sf.project(xb, bv, 25, batch=batch, precision="fp32", graph=True, out=bufs)
+        torch.cuda.synchronize()
+        assert torch.equal(bufs.xi, eager.xi) and torch.equal(bufs.lam, eager.lam), rep
+        assert torch.equal(bufs.resid, eager.resid), rep
+        # eager work between replays
+        tmp = (xb * 2.0).sum()
+        torch.cuda.synchronize()
+        assert torch.isfinite(tmp)
+
+
+def test_autotune_writes_cache_and_keeps_results(P, tmp_path, monkeypatch):
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("SWARMSF_TUNE_CACHE", str(cache))
+    probs = ragged_problems()
+    sf = P.SafetyFilter([p.cfg for p in probs])
+    batch = P.Batch([(i, p.xi_bar.shape[0]) for i, p in enumerate(probs)])
+    xb, bv = pack(probs)
+    ref = sf.project(xb, bv, 20, batch=batch, precision="fp32")
+    tuned = sf.project(xb, bv, 20, batch=batch, precision="fp32", autotune=True)
+    torch.cuda.synchronize()
+    assert torch.equal(ref.xi, tuned.xi) and torch.equal(ref.lam, tuned.lam)
+    text = cache.read_text()
+    assert '"grid":' in text and "gfx950" in text
+
+
+def test_ragged_3000_full_size(P):
+    """3000 problems (1000 each of 8, 16, 32 robots), 1..256 samples each, 300 iterations, in one
+    persistent launch; sampled problems of each size against the oracle."""
+    wl = W.ragged()
+    cfgs = sorted({p.cfg for p in wl.problems}, key=lambda c: c.n_robots)
+    slot = {c: i for i, c in enumerate(cfgs)}
+    sf = P.SafetyFilter(cfgs)
+    batch = P.Batch([(slot[p.cfg], p.xi_bar.shape[0]) for p in wl.problems])
+    xb, bv = pack(wl.problems)
+    out = sf.project(xb, bv, wl.iters, batch=batch, precision="fp32", autotune=True)
+    torch.cuda.synchronize()
+    assert torch.isfinite(out.xi).all()
+    offs = np.cumsum([0] + [p.xi_bar.size for p in wl.problems])
+    seen = set()
+    for k, p in enumerate(wl.problems):
+        n = p.cfg.n_robots
+        if n in seen:
+            continue
+        seen.add(n)
+        s = O.build_system(p.cfg)
+        take = min(2, p.xi_bar.shape[0])
+        rx, _, _ = O.sf_project(s, torch.tensor(p.xi_bar[:take]), torch.tensor(p.bvals), wl.iters)
+        g = out.xi[offs[k]:offs[k] + take * p.xi_bar[0].size].reshape(rx.shape).cpu().double()
+        e = ((g - rx).abs().reshape(take, -1).amax(1) / rx.abs().reshape(take, -1).amax(1)).numpy()
+        print(f"ragged n={n} problem {k}: rel err {e}", flush=True)
+        assert e.max() <= 1e-4
