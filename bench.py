@@ -1,11 +1,14 @@
 """Benchmark of the batched safety filter on one MI355X.
 
-One step = one sf_project call over the whole workload (every sample, every iteration,
-final residual), inputs resident in HBM.  Prints one JSON line.
+One step = one sf_project call over the whole workload (every sample, every iteration, final
+residual), inputs resident in HBM.  The headline form (BF16-MFMA basis products with fp32
+correction terms by default) is timed for exactly --steps calls; the plain FP32 solver is timed
+beside it on the same inputs, and both are judged at the same final feasibility tolerance.
+Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -17,12 +20,10 @@ if ROOT not in sys.path:
 FEAS_TOL = 1e-3          # m, m/s, m/s^2 at the grid times, checked in FP64
 PEAKS = {                # published MI355X peaks
     "fp32_vector_tflops": 157.3,
-    "bf16_mfma_tflops": 2500.0,
-    "fp16_mfma_tflops": 2500.0,
-    "fp32_mfma_tflops": 157.3,
     "fp64_vector_tflops": 78.6,
-    "hbm_gbs": 8000.0,
 }
+DTYPES = {"fp64": "f64", "fp32": "f32", "bf16": "f32 state, bf16 MFMA basis products",
+          "fp16": "f32 state, f16 MFMA basis products"}
 
 
 def flops_per_sample_iter(cfg):
@@ -37,6 +38,32 @@ def flops_per_sample_iter(cfg):
             + 2 * Np * H * D + 5 * n * D * mf + 2 * D * (n * mf) ** 2)
 
 
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in ("sf_fast.hip", "sf_fast.h", "sf_internal.h"):
+        with open(os.path.join(ROOT, "paper_2501_19042_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it
+    was taken on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"fast_project_traffic_{workload}_{precision}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    kib = float(vals["fetch_kib_per_dispatch"]) * float(vals["fetch_scale"]) + \
+        float(vals["write_kib_per_dispatch"]) * float(vals["write_scale"])
+    return int(kib * 1024)
+
+
 def cpu_baseline(workload, n_samples, iters):
     """The FP64 oracle on a bounded sample of the same workload, on the host cores."""
     import torch
@@ -48,10 +75,42 @@ def cpu_baseline(workload, n_samples, iters):
     t0 = time.perf_counter()
     O.sf_project(s, xb, bv, iters)
     dt = time.perf_counter() - t0
-    return {"value": n_samples / dt, "unit": "projections/s", "cores": torch.get_num_threads(),
+    return {"value": round(n_samples / dt, 2), "unit": "projections/s", "cores": torch.get_num_threads(),
             "kind": "oracle",
             "sample": f"first {n_samples} of {p.xi_bar.shape[0]} samples, {iters} iterations, "
                       f"FP64 torch CPU ({dt:.1f} s)"}
+
+
+def run_form(sf, xb, bv, K, prec, steps, warmup, generic, graph):
+    """Time `steps` calls of one form; returns (ms per call, outputs)."""
+    import torch
+    S = xb.shape[0]
+    bufs = None
+    if graph:
+        from paper_2501_19042_amd import ProjectResult
+        bufs = ProjectResult(torch.empty_like(xb), torch.empty_like(xb),
+                             torch.empty((S, 2), dtype=xb.dtype, device=xb.device), None)
+    call = lambda: sf.project(xb, bv, K, precision=prec, generic=generic, graph=graph, out=bufs)
+    out = None
+    for _ in range(warmup):
+        out = call()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        out = call()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps, out
+
+
+def judge(sf, out, bv, prec):
+    viol = sf.feasibility(out.xi, bv, precision=prec).cpu()
+    worst = viol[:, :3].amax(1).clamp_min(viol[:, 3])
+    feas = worst <= FEAS_TOL
+    return int(feas.sum()), float(worst.quantile(0.99)), float(worst.max())
 
 
 def main():
@@ -60,15 +119,22 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="swarm16", choices=["swarm16", "swarm32", "tiny2d"])
-    ap.add_argument("--precision", default="fp32")
-    ap.add_argument("--cpu-samples", type=int, default=128)
+    ap.add_argument("--precision", default="bf16", choices=["fp64", "fp32", "bf16", "fp16"])
+    ap.add_argument("--compare", default="fp32", choices=["fp32", "bf16", "fp16", "none"],
+                    help="second form timed beside the headline one")
+    ap.add_argument("--cpu-samples", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--generic", action="store_true", help="force the generic (non-MFMA) kernel")
+    ap.add_argument("--graph", action="store_true", help="replay the launch as a captured hipGraph")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 3 device copies of 256 MiB (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; --gpus above 1 is not supported "
+                                   "(samples shard across GPUs without communication, see the design notes)"}))
+        sys.exit(2)
+    import torch
     if args.copy_calibration:
-        import torch
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
@@ -76,12 +142,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_per_copy": src.numel() * 4}))
         return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus above 1 is not supported "
-                                   "(samples shard across GPUs without communication, see the design notes)"}))
-        sys.exit(2)
 
-    import torch
     import workloads as W
     from paper_2501_19042_amd import SafetyFilter
 
@@ -96,29 +157,14 @@ def main():
     S = xb.shape[0]
     K = wl.iters
 
-    for _ in range(args.warmup):
-        out = sf.project(xb, bv, K, precision=prec, generic=args.generic)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        out = sf.project(xb, bv, K, precision=prec, generic=args.generic)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
-
-    viol = sf.feasibility(out.xi, bv, precision=prec).cpu()
-    feas = (viol[:, :3] <= FEAS_TOL).all(1) & (viol[:, 3] <= FEAS_TOL)
-    n_conv = int(feas.sum())
+    ms, out = run_form(sf, xb, bv, K, prec, args.steps, args.warmup, args.generic, args.graph)
+    n_conv, p99, vmax = judge(sf, out, bv, prec)
     value = n_conv / (ms / 1e3)
 
     W_it = flops_per_sample_iter(p.cfg)
-    flops = W_it * S * K
-    achieved = flops / (ms / 1e3) / 1e12
+    achieved = W_it * S * K / (ms / 1e3) / 1e12
     peak = PEAKS["fp64_vector_tflops"] if prec == "fp64" else PEAKS["fp32_vector_tflops"]
+    traffic = None if (args.generic or prec == "fp64") else measured_traffic(args.workload, prec)
     line = {
         "metric": "converged SF projections/sec (16 robots, 3D); BF16-MFMA vs FP32 at equal residual",
         "value": round(value, 1),
@@ -130,17 +176,30 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16+f32", "fp16": "f16+f32"}[prec],
+        "dtype": DTYPES[prec],
         "data": "synthetic (seeded straight-line Bernstein fits + Gaussian coefficient noise)",
         "config": {"workload": wl.name, "samples": S, "robots": p.cfg.n_robots, "dims": p.cfg.dims,
                    "degree": p.cfg.degree, "horizon": p.cfg.horizon, "iters": K, "precision": prec,
-                   "kernel": "generic" if args.generic else "mfma"},
-        "converged_fraction": n_conv / S,
+                   "kernel": "generic" if args.generic else "mfma", "graph": args.graph},
+        "converged_fraction": round(n_conv / S, 6),
+        "violation_p99": p99,
+        "violation_max": vmax,
         "all_samples_per_s": round(S / (ms / 1e3), 1),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
-                     "flops_per_sample_iter": W_it, "kernel_ms": round(ms, 4)},
+                     "frac": round(achieved / peak, 4), "traffic": traffic,
+                     "flops_per_sample_iter": W_it, "kernel_ms": round(ms, 4),
+                     "note": "dense algorithmic flops of the method; the MFMA kernel skips exact zeros"},
     }
+    if args.compare != "none" and args.compare != prec and prec != "fp64":
+        ms2, out2 = run_form(sf, xb, bv, K, args.compare, max(3, args.steps // 2), 1, args.generic, False)
+        n2, p99b, vmaxb = judge(sf, out2, bv, args.compare)
+        dev = ((out.xi - out2.xi).abs().reshape(S, -1).amax(1) / out2.xi.abs().reshape(S, -1).amax(1)).cpu()
+        line["compare"] = {
+            "precision": args.compare, "ms_per_step": round(ms2, 4), "value": round(n2 / (ms2 / 1e3), 1),
+            "converged_fraction": round(n2 / S, 6), "violation_p99": p99b, "violation_max": vmaxb,
+            "speedup_of_headline": round(ms2 / ms, 3),
+            "per_sample_rel_deviation_max": float(dev.max()), "per_sample_rel_deviation_median": float(dev.median()),
+        }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_samples, S), K)
     print(json.dumps(line), flush=True)
