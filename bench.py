@@ -81,8 +81,9 @@ def cpu_baseline(workload, n_samples, iters):
                       f"FP64 torch CPU ({dt:.1f} s)"}
 
 
-def run_form(sf, xb, bv, K, prec, steps, warmup, generic, graph):
-    """Time `steps` calls of one form; returns (ms per call, outputs)."""
+def run_form(sf, xb, bv, K, prec, steps, warmup, generic, graph, autotune=True):
+    """Time `steps` calls of one form; returns (ms per call, outputs).  The autotuner (launch
+    shape chosen by timing on this batch) runs inside the first warm-up call."""
     import torch
     S = xb.shape[0]
     bufs = None
@@ -90,9 +91,10 @@ def run_form(sf, xb, bv, K, prec, steps, warmup, generic, graph):
         from paper_2501_19042_amd import ProjectResult
         bufs = ProjectResult(torch.empty_like(xb), torch.empty_like(xb),
                              torch.empty((S, 2), dtype=xb.dtype, device=xb.device), None)
-    call = lambda: sf.project(xb, bv, K, precision=prec, generic=generic, graph=graph, out=bufs)
+    call = lambda: sf.project(xb, bv, K, precision=prec, generic=generic, graph=graph, out=bufs,
+                              autotune=autotune and not generic)
     out = None
-    for _ in range(warmup):
+    for _ in range(max(1, warmup)):
         out = call()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()

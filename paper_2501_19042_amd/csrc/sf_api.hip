@@ -161,6 +161,19 @@ sf_status build_cfg(const sf_config& c, HostCfg& out) {
   d.vmax = vel ? c.vmax : 0.0; d.amax = acc ? c.amax : 0.0;
   d.rho_c = c.rho_coll; d.rho_v = vel ? c.rho_vel : 0.0; d.rho_a = acc ? c.rho_acc : 0.0;
   d.n_rho_c = n * c.rho_coll;
+  d.lip_v = d.lip_a = 0.0;
+  for (int h = 0; h < H; ++h) {
+    double sv = 0.0, sa = 0.0;
+    for (int k = 0; k < m; ++k) {
+      sv += std::fabs(Pd[h * m + k]);
+      sa += std::fabs(Pdd[h * m + k]);
+    }
+    d.lip_v = std::max(d.lip_v, sv);
+    d.lip_a = std::max(d.lip_a, sa);
+  }
+  // round the bounds up so that the fp32 copies used on the device stay upper bounds
+  d.lip_v *= 1.0 + 1e-6;
+  d.lip_a *= 1.0 + 1e-6;
   std::vector<double>& t = out.tab;
   t.clear();
   d.off_basis = t.size();
@@ -368,54 +381,73 @@ std::string tune_signature(sf_handle h, const Plan* p, int precision) {
   return buf;
 }
 
-int tune_lookup(const std::string& sig) {
+bool tune_lookup(const std::string& sig, int* waves, int* grid) {
   const std::string path = tune_cache_path();
-  if (path.empty()) return 0;
+  if (path.empty()) return false;
   FILE* fp = std::fopen(path.c_str(), "r");
-  if (!fp) return 0;
+  if (!fp) return false;
   char line[512];
-  int found = 0;
+  bool found = false;
   while (std::fgets(line, sizeof(line), fp)) {
     char key[256];
-    int grid = 0;
-    if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"grid\": %d", key, &grid) == 2 && sig == key) found = grid;
+    int w = 0, g = 0;
+    if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"waves\": %d, \"grid\": %d", key, &w, &g) == 3 &&
+        sig == key && (w == 2 || w == 4)) {
+      *waves = w;
+      *grid = g;
+      found = true;
+    }
   }
   std::fclose(fp);
   return found;
 }
 
-void tune_store(const std::string& sig, int grid, double ms) {
+void tune_store(const std::string& sig, int waves, int grid, double ms) {
   const std::string path = tune_cache_path();
   if (path.empty()) return;
   FILE* fp = std::fopen(path.c_str(), "a");
   if (!fp) return;
-  std::fprintf(fp, "{\"key\": \"%s\", \"grid\": %d, \"ms\": %.4f}\n", sig.c_str(), grid, ms);
+  std::fprintf(fp, "{\"key\": \"%s\", \"waves\": %d, \"grid\": %d, \"ms\": %.4f}\n", sig.c_str(), waves, grid, ms);
   std::fclose(fp);
 }
 
 sf_status autotune(sf_handle h, const Plan* p, sf::FastPlan& fp, const sf::LaunchArgs& a, int precision) {
-  if (fp.tuned_grid[precision & 3] > 0) return SF_OK;
-  const std::string sig = tune_signature(h, p, precision);
-  const int cached = tune_lookup(sig);
-  if (cached > 0) {
-    fp.tuned_grid[precision & 3] = cached;
+  const int pi = precision & 3;
+  if (fp.tuned_w[pi] > 0) return SF_OK;
+  const std::string sig = tune_signature(h, p, precision) + (fp.batched ? ":persistent" : ":single");
+  int cw = 0, cg = 0;
+  if (tune_lookup(sig, &cw, &cg)) {
+    fp.tuned_w[pi] = cw;
+    fp.tuned_grid[pi] = cg;
     return SF_OK;
   }
-  std::vector<int> cand;
-  for (int k = 1; k <= 4; ++k) cand.push_back(std::min(fp.ncu * k, p->n_items));
-  cand.push_back(p->n_items);
-  std::sort(cand.begin(), cand.end());
-  cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+  // candidates: waves per workgroup x (persistent only) workgroups in flight
+  std::vector<std::pair<int, int>> cand;
+  for (int W : {2, 4}) {
+    if (!fp.batched) {
+      cand.push_back({W, 0});
+      continue;
+    }
+    std::vector<int> grids;
+    for (int k = 1; k <= 6; ++k) grids.push_back(std::min(fp.ncu * k, p->n_items));
+    std::sort(grids.begin(), grids.end());
+    grids.erase(std::unique(grids.begin(), grids.end()), grids.end());
+    for (int g : grids) cand.push_back({W, g});
+  }
   sf::LaunchArgs t = a;
-  t.iters = std::max(1, std::min(a.iters, 10));
+  t.iters = std::max(1, std::min(a.iters, 20));
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(SF_EDEVICE, "events");
-  int best = fp.grid;
+  auto run = [&](const std::pair<int, int>& c) {
+    return fp.batched ? sf::fast_launch_batched(fp, t, h->d_tab32, h->d_a16, precision, c.second, c.first)
+                      : sf::fast_launch_single(fp, t, h->d_tab32, h->d_a16, precision, c.first);
+  };
+  std::pair<int, int> best = cand[0];
   float best_ms = 1e30f;
-  for (int g : cand) {
-    hipError_t e = sf::fast_launch_batched(fp, t, h->d_tab32, h->d_a16, precision, g);   // warm-up
+  for (const auto& c : cand) {
+    hipError_t e = run(c);                                  // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, a.stream);
-    if (e == hipSuccess) e = sf::fast_launch_batched(fp, t, h->d_tab32, h->d_a16, precision, g);
+    if (e == hipSuccess) e = run(c);
     if (e == hipSuccess) e = hipEventRecord(e1, a.stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.0f;
@@ -427,13 +459,14 @@ sf_status autotune(sf_handle h, const Plan* p, sf::FastPlan& fp, const sf::Launc
     }
     if (ms < best_ms) {
       best_ms = ms;
-      best = g;
+      best = c;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  fp.tuned_grid[precision & 3] = best;
-  tune_store(sig, best, best_ms);
+  fp.tuned_w[pi] = best.first;
+  fp.tuned_grid[pi] = best.second;
+  tune_store(sig, best.first, best.second, best_ms);
   return SF_OK;
 }
 
@@ -600,7 +633,7 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
     st = pick_tile(h, p, elem, generic_bytes, &a.tile, &a.lds_bytes);
     if (st != SF_OK) return st;
   }
-  if (fp && fp->batched && (flags & SF_AUTOTUNE)) {
+  if (fp && (flags & SF_AUTOTUNE)) {
     st = autotune(h, p, *fp, a, precision);
     if (st != SF_OK) return st;
   }
@@ -619,6 +652,7 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
   if (flags & SF_USE_GRAPH) {
     std::vector<uintptr_t> key = {(uintptr_t)precision, (uintptr_t)flags, (uintptr_t)iters, (uintptr_t)a.ckpt_every,
                                   (uintptr_t)fp, (uintptr_t)(fp ? fp->tuned_grid[precision & 3] : 0),
+                                  (uintptr_t)(fp ? fp->tuned_w[precision & 3] : 0),
                                   (uintptr_t)xi_bar, (uintptr_t)bvals, (uintptr_t)xi0, (uintptr_t)lam0,
                                   (uintptr_t)xi_out, (uintptr_t)lam_out, (uintptr_t)resid_out, (uintptr_t)ckpt};
     hipGraphExec_t exec = nullptr;

@@ -13,8 +13,8 @@ struct FastPlan {
   bool ok = false;              // the batch is covered by the fast kernels
   int R = 0;                    // robot tiles of 16 (single-shape batches)
   int KS = 0;                   // k-steps of 4 coefficients (maximum over the batch)
-  int TQ = 0;                   // time tiles per wave (maximum over the batch)
-  size_t lds_bytes = 0;
+  int W = 4;                    // waves per workgroup (2 or 4); time tiles are dealt round-robin
+  size_t lds_bytes_w[2] = {0, 0};       // LDS per workgroup for W = 2 and W = 4
   // persistent launch over a ragged batch (mixed swarm sizes, or requested)
   bool batched = false;
   WorkItem* d_items_sorted = nullptr;   // work items, most expensive first
@@ -22,6 +22,7 @@ struct FastPlan {
   int ncu = 0;
   int grid = 0;                         // default persistent workgroups
   int tuned_grid[4] = {0, 0, 0, 0};     // autotuned persistent workgroups per precision (0 = not tuned)
+  int tuned_w[4] = {0, 0, 0, 0};        // autotuned waves per workgroup per precision (0 = not tuned)
 };
 
 sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<DevProblem>& probs,
@@ -29,7 +30,9 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
 void fast_plan_free(FastPlan& p);
 hipError_t fast_launch(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16, int precision);
 hipError_t fast_launch_batched(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16,
-                               int precision, int grid);
+                               int precision, int grid, int W);
+hipError_t fast_launch_single(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16,
+                              int precision, int W);
 
 // Number of 16-byte entries of the 16-bit S1 basis-operand table of one config (per precision).
 int64_t a16_entries(const DevCfg& c);

@@ -88,7 +88,7 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
 // accesses of 8 consecutive lanes fall in distinct banks; boxes bb [robot][8]; active list.
 constexpr int kRS = 20;
 struct FastLds {
-  int xi, lam, xb, xprev, gpart, xp, dlt, dbar, corr, ybuf, ybar, pairs, red, tiles, per_wave, total;
+  int xi, lam, xb, xprev, gpart, xp, dlt, dbar, corr, ybuf, ybar, pairs, red, ball, tiles, per_wave, total;
   int xt, ct, bb, plist;   // offsets inside one wave's tile region
 };
 
@@ -109,6 +109,8 @@ __host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W) 
   p.ybar = o; o += 3 * (c.mf > 0 ? c.mf : 1);
   p.pairs = o; o += Npmax;
   p.red = o; o += 2 * 64 * W;
+  p.ball = o; o += 10 * nr + 4;             // per robot: margin_v, drift_v, margin_a, drift_a, max|v|^2,
+                                           // max|a|^2, and per (robot, axis) max|dxi|; flags
   o = (o + 3) & ~3;                       // 16-byte alignment of the tile buffers
   p.xt = 0;
   p.ct = 3 * nr * kRS;
@@ -160,7 +162,7 @@ struct FastArgs {
 };
 
 // The whole solve of one work item (its samples) by one workgroup.
-template <int R, int KS, int W, int TQ, int MP>
+template <int R, int KS, int W, int MP>
 __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem) {
   const DevCfg* __restrict__ cfgs = A.cfgs;
   const float* __restrict__ tab = A.tab;
@@ -192,6 +194,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
     const int nDm = n * 3 * m, nDf = n * 3 * mf, nD6 = n * 3 * kNFix;
     const int Np = n * (n - 1) / 2;
     const int NT = (H + 15) / 16;
+    const int TQ = (NT + W - 1) / W;            // time tiles per wave
     const float* basis = tab + c.off_basis;
     const float* X1 = tab + c.off_X1;
     const float* X01 = tab + c.off_X01;
@@ -214,6 +217,16 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
     float* sybar = smem + L.ybar;
     int* spairs = reinterpret_cast<int*>(smem + L.pairs);
     float* sred = smem + L.red;
+    // bound-ball drift tracking (see the velocity/acceleration section of the tile loop)
+    float* s_mv = smem + L.ball;             // margin of the velocity bound at the last evaluation
+    float* s_dv = s_mv + NR;                 // accumulated bound on the velocity drift since then
+    float* s_ma = s_dv + NR;
+    float* s_da = s_ma + NR;
+    unsigned* s_vmx = reinterpret_cast<unsigned*>(s_da + NR);   // max ||v||^2 (float bits) this iteration
+    unsigned* s_amx = s_vmx + NR;
+    unsigned* s_dxi = s_amx + NR;            // max |change of a free coefficient| per (robot, axis)
+    int* s_flag = reinterpret_cast<int*>(s_dxi + 3 * NR);
+    const float Lv = (float)c.lip_v, La = (float)c.lip_a;
     float* wbuf = smem + L.tiles + wave * L.per_wave;
     float* Xt = wbuf + L.xt;
     float* Ct = wbuf + L.ct;
@@ -250,6 +263,12 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         for (int s = 0; s < kNFix; ++s) acc = fmaf(Bmap[r * kNFix + s], bv[row * kNFix + s], acc);
         sxp[q] = acc;
       }
+      for (int q = tid; q < NR; q += nthr) {
+        s_mv[q] = -1.0f; s_dv[q] = 0.0f; s_ma[q] = -1.0f; s_da[q] = 0.0f;
+        s_vmx[q] = 0u; s_amx[q] = 0u;
+        s_dxi[3 * q] = s_dxi[3 * q + 1] = s_dxi[3 * q + 2] = 0u;
+      }
+      if (tid == 0) s_flag[0] = 0;
       __syncthreads();
       for (int q = tid; q < nD6; q += nthr) {
         const int row = q / kNFix, r = q - row * kNFix;
@@ -286,6 +305,26 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         }
         if (resid_out && k == iters - 1)
           for (int q = tid; q < nDm; q += nthr) sxprev[q] = sxi[q];
+        // Velocity/acceleration at every grid time move by at most L * ||max_k |d xi_{i,d,k}| ||_2
+        // per step (L = max_t sum_k |basis row|).  While the accumulated drift of every robot stays
+        // below its margin to the bound at the last evaluation, the ball residuals are exactly zero
+        // and S1/S3/S4 for that basis are skipped.  Iterations 0 and 1 always evaluate (the pinned
+        // coefficients change in the first step).
+        for (int q = tid; q < n; q += nthr) {
+          const float d0 = __uint_as_float(s_dxi[3 * q]), d1 = __uint_as_float(s_dxi[3 * q + 1]);
+          const float d2 = __uint_as_float(s_dxi[3 * q + 2]);
+          const float dn = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+          s_dxi[3 * q] = s_dxi[3 * q + 1] = s_dxi[3 * q + 2] = 0u;
+          const float dv = s_dv[q] + Lv * dn, da = s_da[q] + La * dn;
+          s_dv[q] = dv;
+          s_da[q] = da;
+          int f = 0;
+          if (c.vel_on && dv >= s_mv[q] - 1e-4f * vmax) f |= 1;
+          if (c.acc_on && da >= s_ma[q] - 1e-4f * amax) f |= 2;
+          if (f) atomicOr(s_flag, f);
+        }
+        __syncthreads();
+        const int eval_flags = (k < 2) ? 3 : s_flag[0];
         // S1 B operand: xi^T, lane (col, grp) holds robot col, coefficient 4 s + grp
         float bx[MP == 0 ? R : 1][3][KS];
         typename Half<MP == 0 ? 1 : MP>::V hb1[MP == 0 ? 1 : R][3], hb2[MP == 0 ? 1 : R][3];
@@ -388,23 +427,30 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
 #pragma unroll
           for (int b = 1; b < 3; ++b) {
             const bool on = b == 1 ? c.vel_on : c.acc_on;
-            if (!on) continue;
+            if (!on || !(eval_flags & b)) continue;
             const float lim = b == 1 ? vmax : amax;
             f4 Y[R][3];
             s1(q, tau, b, Y);
             bool nz = false;
+            unsigned* smx = b == 1 ? s_vmx : s_amx;
 #pragma unroll
-            for (int rr = 0; rr < R; ++rr)
+            for (int rr = 0; rr < R; ++rr) {
+              float mx = 0.0f;
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const float vx = Y[rr][0][r], vy = Y[rr][1][r], vz = Y[rr][2][r];
                 const float ss = vx * vx + vy * vy + vz * vz;
+                mx = fmaxf(mx, ss);
                 const float f = ss > lim * lim ? 1.0f - lim * rsqrtf(ss) : 0.0f;
                 Y[rr][0][r] = f * vx;
                 Y[rr][1][r] = f * vy;
                 Y[rr][2][r] = f * vz;
                 nz |= f != 0.0f;
               }
+              mx = fmaxf(mx, __shfl_xor(mx, 16));
+              mx = fmaxf(mx, __shfl_xor(mx, 32));
+              if (grp == 0 && 16 * rr + col < n) atomicMax(smx + 16 * rr + col, __float_as_uint(mx));
+            }
             if (ballot(nz) != 0) {
               float b4[4];
 #pragma unroll
@@ -498,6 +544,19 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
               }
         }
         __syncthreads();
+        for (int q = tid; q < n; q += nthr) {
+          if (eval_flags & 1) {
+            s_mv[q] = vmax - sqrtf(__uint_as_float(s_vmx[q]));
+            s_dv[q] = 0.0f;
+            s_vmx[q] = 0u;
+          }
+          if (eval_flags & 2) {
+            s_ma[q] = amax - sqrtf(__uint_as_float(s_amx[q]));
+            s_da[q] = 0.0f;
+            s_amx[q] = 0u;
+          }
+        }
+        if (tid == 0) s_flag[0] = 0;
         // multiplier step and QP step on the free coefficients
         for (int q = tid; q < nDm; q += nthr) {
           float gq = 0.0f;
@@ -528,6 +587,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             acc = fmaf(X01[f * mf + f2], sybar[d * mf + f2], acc);
           }
           sxi[row * m + 3 + f] += acc;
+          atomicMax(s_dxi + row, __float_as_uint(fabsf(acc)));
         }
         if (k == 0) {
           for (int q = tid; q < nD6; q += nthr) {
@@ -687,17 +747,17 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
 }
 
 // One workgroup per work item (grid-stride), single shape class.
-template <int R, int KS, int W, int TQ, int MP, int WPE>
+template <int R, int KS, int W, int MP, int WPE>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 fast_project_kernel(FastArgs A) {
   extern __shared__ __align__(16) float smem[];
-  for (int it = blockIdx.x; it < A.n_items; it += gridDim.x) fast_item<R, KS, W, TQ, MP>(A, it, smem);
+  for (int it = blockIdx.x; it < A.n_items; it += gridDim.x) fast_item<R, KS, W, MP>(A, it, smem);
 }
 
 // Persistent kernel over a ragged batch: workgroups pull work items (sorted by decreasing cost
 // on the host) from an atomic queue until it is empty; each item runs the body for its swarm
 // size (up to 16 robots, or up to 32).  Every wave reaches the exit once the queue is drained.
-template <int KS, int W, int TQ, int MP, int WPE>
+template <int KS, int W, int MP, int WPE>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 fast_batched_kernel(FastArgs A, int* __restrict__ queue) {
   extern __shared__ __align__(16) float smem[];
@@ -709,8 +769,8 @@ fast_batched_kernel(FastArgs A, int* __restrict__ queue) {
     __syncthreads();
     if (it >= A.n_items) break;
     const int n = A.cfgs[A.probs[A.items[it].problem].cfg].n;
-    if (n <= 16) fast_item<1, KS, W, TQ, MP>(A, it, smem);
-    else fast_item<2, KS, W, TQ, MP>(A, it, smem);
+    if (n <= 16) fast_item<1, KS, W, MP>(A, it, smem);
+    else fast_item<2, KS, W, MP>(A, it, smem);
   }
 }
 
@@ -718,7 +778,7 @@ __global__ void reset_queue_kernel(int* queue) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0;
 }
 
-// Kernel instances: R robot tiles of 16, KS k-steps of 4 coefficients, W waves, TQ tiles per wave.
+// Kernel instances: R robot tiles of 16, KS k-steps of 4 coefficients, W waves per workgroup.
 constexpr int kW = 4;
 // Target waves per SIMD: the register budget that fits each instance without spills.
 constexpr int waves_per_simd(int R, int MP) { return (R == 1 && MP == 0) ? 3 : (R == 1 ? 2 : (MP == 0 ? 2 : 1)); }
@@ -734,13 +794,13 @@ FastArgs make_fast_args(const LaunchArgs& a, const float* tab32, const uint4* a1
   return f;
 }
 
-template <int R, int KS, int TQ, int MP>
+template <int R, int KS, int W, int MP>
 hipError_t launch_instance(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16) {
-  auto kern = fast_project_kernel<R, KS, kW, TQ, MP, waves_per_simd(R, MP)>;
+  auto kern = fast_project_kernel<R, KS, W, MP, waves_per_simd(R, MP)>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes_w[W / 2 - 1]);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(a.n_items), dim3(64 * kW), p.lds_bytes, a.stream, make_fast_args(a, tab32, a16));
+  hipLaunchKernelGGL(kern, dim3(a.n_items), dim3(64 * W), p.lds_bytes_w[W / 2 - 1], a.stream, make_fast_args(a, tab32, a16));
   return hipGetLastError();
 }
 
@@ -821,7 +881,7 @@ void a16_fill(const DevCfg& c, const double* P3, int precision, uint16_t* out) {
 
 namespace {
 
-bool cfg_supported(const DevCfg& c) { return c.D == 3 && c.n <= 32 && c.m <= 16 && c.H <= 16 * kW * 2; }
+bool cfg_supported(const DevCfg& c) { return c.D == 3 && c.n <= 32 && c.m <= 16 && c.H <= 256; }
 
 // Relative cost of one sample-iteration: S1 MFMA work grows with the robot tiles and time tiles,
 // the broad phase with the number of pairs.
@@ -840,22 +900,34 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
   if (probs.empty()) return SF_OK;
   bool mixed = false;
   int maxKS = 2, maxNT = 1;
-  size_t lds = 0;
   for (const DevProblem& p : probs) {
     const DevCfg& c = cfgs[p.cfg];
     if (!cfg_supported(c)) return SF_OK;                 // generic path
     if (p.cfg != probs[0].cfg) mixed = true;
     maxKS = std::max(maxKS, (c.m + 3) / 4);
     maxNT = std::max(maxNT, (c.H + 15) / 16);
-    lds = std::max(lds, (size_t)fast_lds_plan(c, c.n <= 16 ? 1 : 2, kW).total * 4);
+    for (int wi = 0; wi < 2; ++wi)
+      out.lds_bytes_w[wi] = std::max(out.lds_bytes_w[wi], (size_t)fast_lds_plan(c, c.n <= 16 ? 1 : 2, 2 * (wi + 1)).total * 4);
   }
-  if (lds > 160 * 1024) return SF_OK;
+  if (out.lds_bytes_w[1] > 160 * 1024) return SF_OK;
   const DevCfg& c0 = cfgs[probs[0].cfg];
   out.KS = maxKS;
-  out.TQ = (maxNT + kW - 1) / kW;
   out.R = c0.n <= 16 ? 1 : 2;
-  out.lds_bytes = lds;
   out.batched = mixed || persistent;
+  {
+    // default waves per workgroup: 4, unless 2 lets every work item be resident at once
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    out.ncu = ncu > 0 ? ncu : 256;
+    auto slots = [&](int W) {
+      const int by_waves = (4 * waves_per_simd(out.batched ? 2 : out.R, 0)) / W;
+      const int by_lds = (int)((160 * 1024) / std::max<size_t>(out.lds_bytes_w[W / 2 - 1], 1));
+      return (int64_t)std::max(1, std::min(by_waves, by_lds)) * out.ncu;
+    };
+    const int64_t ni = (int64_t)items.size();
+    out.W = (ni > slots(4) && ni <= slots(2)) ? 2 : 4;
+  }
   if (out.batched) {
     // longest-processing-time order: most expensive work items first
     std::vector<std::pair<double, int>> order(items.size());
@@ -876,11 +948,7 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
       g_fast_err = "persistent plan allocation failed";
       return SF_ENOMEM;
     }
-    int dev = 0, ncu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    out.ncu = ncu > 0 ? ncu : 256;
-    const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(lds, 1))));
+    const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(out.lds_bytes_w[out.W / 2 - 1], 1))));
     out.grid = std::min<int>((int)items.size(), out.ncu * per_cu);
   }
   out.ok = true;
@@ -897,29 +965,30 @@ void fast_plan_free(FastPlan& p) {
 
 namespace {
 
-template <int KS, int TQ, int MP>
+template <int KS, int W, int MP>
 hipError_t launch_batched(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16, int grid) {
-  auto kern = fast_batched_kernel<KS, kW, TQ, MP, waves_per_simd(2, MP)>;
+  auto kern = fast_batched_kernel<KS, W, MP, waves_per_simd(2, MP)>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes);
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes_w[W / 2 - 1]);
   if (e != hipSuccess) return e;
   FastArgs f = make_fast_args(a, tab32, a16);
   f.items = p.d_items_sorted;
   hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, a.stream, p.d_queue);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kW), p.lds_bytes, a.stream, f, p.d_queue);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * W), p.lds_bytes_w[W / 2 - 1], a.stream, f, p.d_queue);
   return hipGetLastError();
 }
 
 template <int MP>
-hipError_t launch_batched_mp(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16, int grid) {
-  const int key = p.KS * 10 + p.TQ;
+hipError_t launch_batched_mp(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16, int grid,
+                             int W) {
+  const int key = p.KS * 10 + W;
   switch (key) {
-    case 21: return launch_batched<2, 1, MP>(p, a, tab32, a16, grid);
     case 22: return launch_batched<2, 2, MP>(p, a, tab32, a16, grid);
-    case 31: return launch_batched<3, 1, MP>(p, a, tab32, a16, grid);
+    case 24: return launch_batched<2, 4, MP>(p, a, tab32, a16, grid);
     case 32: return launch_batched<3, 2, MP>(p, a, tab32, a16, grid);
-    case 41: return launch_batched<4, 1, MP>(p, a, tab32, a16, grid);
+    case 34: return launch_batched<3, 4, MP>(p, a, tab32, a16, grid);
     case 42: return launch_batched<4, 2, MP>(p, a, tab32, a16, grid);
+    case 44: return launch_batched<4, 4, MP>(p, a, tab32, a16, grid);
     default:
       g_fast_err = "no persistent kernel instance for this shape";
       return hipErrorNotSupported;
@@ -929,12 +998,12 @@ hipError_t launch_batched_mp(const FastPlan& p, const LaunchArgs& a, const float
 }  // namespace
 
 hipError_t fast_launch_batched(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16,
-                               int precision, int grid) {
+                               int precision, int grid, int W) {
   const uint4* t = static_cast<const uint4*>(a16);
   switch (precision) {
-    case SF_FP32: return launch_batched_mp<0>(p, a, tab32, t, grid);
-    case SF_BF16: return launch_batched_mp<1>(p, a, tab32, t, grid);
-    case SF_FP16: return launch_batched_mp<2>(p, a, tab32, t, grid);
+    case SF_FP32: return launch_batched_mp<0>(p, a, tab32, t, grid, W);
+    case SF_BF16: return launch_batched_mp<1>(p, a, tab32, t, grid, W);
+    case SF_FP16: return launch_batched_mp<2>(p, a, tab32, t, grid, W);
     default:
       g_fast_err = "precision not implemented in the MFMA kernels";
       return hipErrorNotSupported;
@@ -942,19 +1011,19 @@ hipError_t fast_launch_batched(const FastPlan& p, const LaunchArgs& a, const flo
 }
 
 template <int MP>
-hipError_t launch_mp(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16) {
-  const int key = p.R * 100 + p.KS * 10 + p.TQ;
+hipError_t launch_mp(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16, int W) {
+  const int key = p.R * 100 + p.KS * 10 + W;
   switch (key) {
-    case 121: return launch_instance<1, 2, 1, MP>(p, a, tab32, a16);
     case 122: return launch_instance<1, 2, 2, MP>(p, a, tab32, a16);
-    case 131: return launch_instance<1, 3, 1, MP>(p, a, tab32, a16);
+    case 124: return launch_instance<1, 2, 4, MP>(p, a, tab32, a16);
     case 132: return launch_instance<1, 3, 2, MP>(p, a, tab32, a16);
-    case 141: return launch_instance<1, 4, 1, MP>(p, a, tab32, a16);
+    case 134: return launch_instance<1, 3, 4, MP>(p, a, tab32, a16);
     case 142: return launch_instance<1, 4, 2, MP>(p, a, tab32, a16);
-    case 231: return launch_instance<2, 3, 1, MP>(p, a, tab32, a16);
+    case 144: return launch_instance<1, 4, 4, MP>(p, a, tab32, a16);
     case 232: return launch_instance<2, 3, 2, MP>(p, a, tab32, a16);
-    case 241: return launch_instance<2, 4, 1, MP>(p, a, tab32, a16);
+    case 234: return launch_instance<2, 3, 4, MP>(p, a, tab32, a16);
     case 242: return launch_instance<2, 4, 2, MP>(p, a, tab32, a16);
+    case 244: return launch_instance<2, 4, 4, MP>(p, a, tab32, a16);
     default:
       g_fast_err = "no kernel instance for this shape";
       return hipErrorNotSupported;
@@ -962,15 +1031,21 @@ hipError_t launch_mp(const FastPlan& p, const LaunchArgs& a, const float* tab32,
 }
 
 hipError_t fast_launch(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16, int precision) {
+  const int W = p.tuned_w[precision & 3] > 0 ? p.tuned_w[precision & 3] : p.W;
   if (p.batched) {
     const int g = p.tuned_grid[precision & 3] > 0 ? p.tuned_grid[precision & 3] : p.grid;
-    return fast_launch_batched(p, a, tab32, a16, precision, g);
+    return fast_launch_batched(p, a, tab32, a16, precision, g, W);
   }
+  return fast_launch_single(p, a, tab32, a16, precision, W);
+}
+
+hipError_t fast_launch_single(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16,
+                              int precision, int W) {
   const uint4* t = static_cast<const uint4*>(a16);
   switch (precision) {
-    case SF_FP32: return launch_mp<0>(p, a, tab32, t);
-    case SF_BF16: return launch_mp<1>(p, a, tab32, t);
-    case SF_FP16: return launch_mp<2>(p, a, tab32, t);
+    case SF_FP32: return launch_mp<0>(p, a, tab32, t, W);
+    case SF_BF16: return launch_mp<1>(p, a, tab32, t, W);
+    case SF_FP16: return launch_mp<2>(p, a, tab32, t, W);
     default:
       g_fast_err = "precision not implemented in the MFMA kernels";
       return hipErrorNotSupported;
