@@ -13,7 +13,8 @@ struct FastPlan {
   bool ok = false;              // the batch is covered by the fast kernels
   int R = 0;                    // robot tiles of 16 (single-shape batches)
   int KS = 0;                   // k-steps of 4 coefficients (maximum over the batch)
-  int W = 4;                    // waves per workgroup (2 or 4); time tiles are dealt round-robin
+  int Wp[4] = {4, 4, 4, 4};     // default waves per workgroup (2 or 4) per precision; time tiles
+                                // are dealt round-robin to the waves
   size_t lds_bytes_w[2] = {0, 0};       // LDS per workgroup for W = 2 and W = 4
   // persistent launch over a ragged batch (mixed swarm sizes, or requested)
   bool batched = false;
@@ -38,7 +39,8 @@ hipError_t fast_launch_single(const FastPlan& p, const LaunchArgs& a, const floa
 int64_t a16_entries(const DevCfg& c);
 // Fill the table for one config: [tile][basis][instruction][lane] of 8 x 16-bit values.
 void a16_fill(const DevCfg& c, const double* P3, int precision, uint16_t* out);
-// fp32 S1 basis operands: [tile][basis][lane][4] floats (16-byte entries).
+// fp32 basis operands: [tile][basis][S1 A operand, S4 B operand scaled by rho][lane][4] floats
+// (16-byte entries).
 int64_t a32_entries(const DevCfg& c);
 void a32_fill(const DevCfg& c, const double* P3, float* out);
 std::string fast_last_error();

@@ -84,16 +84,19 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
 }
 
 // LDS plan (in 4-byte words).  Per-wave tile buffers: positions Xt and collision residual
-// accumulator Ct as [axis][robot (16R)][time], rows padded to kRS words so that the 16-byte
-// accesses of 8 consecutive lanes fall in distinct banks; boxes bb [robot][8]; active list.
-constexpr int kRS = 20;
+// accumulator Ct as [axis][robot (16R)][time] with 16-word rows whose four 16-byte chunks are
+// XOR-swizzled by the robot index (tile_at), so that the 16-byte accesses of 16 consecutive lanes
+// hit distinct banks; boxes bb [robot][8]; list of the pairs that survive the broad phase.  Once
+// its time tiles are done, a wave reuses its own region for its partial back-projection (nDm
+// words) and, after the final residual pass, for its partial sums.
+constexpr int kQPRow = 12;               // padded row of the QP matrices in LDS (m_f <= 10)
 struct FastLds {
-  int xi, lam, xb, xprev, gpart, xp, dlt, dbar, corr, ybuf, ybar, pairs, red, ball, tiles, per_wave, total;
+  int xi, lam, xb, xprev, dbar, corr, pairs, vmx, amx, dxi, qp, tiles, per_wave, total;
   int xt, ct, bb, plist;   // offsets inside one wave's tile region
 };
 
 __host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W) {
-  const int nDm = c.n * 3 * c.m, nDf = c.n * 3 * c.mf, nD6 = c.n * 3 * kNFix;
+  const int nDm = c.n * 3 * c.m, nDf = c.n * 3 * c.mf;
   const int nr = 16 * R, Npmax = nr * (nr - 1) / 2;
   FastLds p;
   int o = 0;
@@ -101,29 +104,67 @@ __host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W) 
   p.lam = o; o += nDm;
   p.xb = o; o += nDm;
   p.xprev = o; o += nDm;
-  p.xp = o; o += nD6;
-  p.dlt = o; o += nD6;
   p.dbar = o; o += 3 * kNFix;
   p.corr = o; o += nDf;
-  p.ybuf = o; o += nDf;
-  p.ybar = o; o += 3 * (c.mf > 0 ? c.mf : 1);
   p.pairs = o; o += Npmax;
-  p.red = o; o += 2 * 64 * W;
-  p.ball = o; o += 10 * nr + 4;             // per robot: margin_v, drift_v, margin_a, drift_a, max|v|^2,
-                                           // max|a|^2, and per (robot, axis) max|dxi|; flags
-  o = (o + 3) & ~3;                       // 16-byte alignment of the tile buffers
+  p.vmx = o; o += W * nr;                  // per wave and robot: max ||v||^2 over the wave's tiles
+  p.amx = o; o += W * nr;                  // same for the acceleration
+  p.dxi = o; o += 3 * nr;                  // per (robot, axis): max |change| of a free coefficient
+  o = (o + 3) & ~3;
+  p.qp = o; o += 2 * c.mf * kQPRow;        // X1, X01 with rows padded to kQPRow floats
+  o = (o + 3) & ~3;                        // 16-byte alignment of the tile buffers
   p.xt = 0;
-  p.ct = 3 * nr * kRS;
-  p.bb = 6 * nr * kRS;
+  p.ct = 3 * nr * 16;
+  p.bb = 6 * nr * 16;
   p.plist = p.bb + 8 * nr;
-  p.per_wave = (p.plist + Npmax + 3) & ~3;
+  int pw = p.plist + Npmax;
+  if (pw < nDm) pw = nDm;
+  if (pw < 128) pw = 128;
+  p.per_wave = (pw + 3) & ~3;
   p.tiles = o;
-  const int tiles_words = W * p.per_wave;
-  const int gpart_words = W * nDm;         // per-wave partial g, aliases the tile buffers
-  p.gpart = o;
-  o += tiles_words > gpart_words ? tiles_words : gpart_words;
+  o += W * p.per_wave;
   p.total = o;
   return p;
+}
+
+// Word offset of (row, t) in a tile buffer; row = axis * 16R + robot, t = 0..15.
+__device__ __forceinline__ int tile_at(int row, int t) {
+  return row * 16 + ((((t >> 2) ^ (row >> 2)) & 3) << 2) + (t & 3);
+}
+
+// Minimum / maximum over the four lanes col, col + 16, col + 32, col + 48 (every lane gets the
+// result), with the row-swap instructions of gfx950 instead of LDS permutes.
+__device__ __forceinline__ float grp_min(float x) {
+  const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  x = fminf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+  const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return fminf(__uint_as_float(b[0]), __uint_as_float(b[1]));
+}
+__device__ __forceinline__ float grp_max(float x) {
+  const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  x = fmaxf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+  const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return fmaxf(__uint_as_float(b[0]), __uint_as_float(b[1]));
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over aligned groups of NR (16 or 32) lanes; every lane of a group gets the same value
+// (each step adds a lane's value and its partner's, and addition is commutative).
+template <int NR>
+__device__ __forceinline__ float group_sum(float v) {
+  v = v + dpp<0xB1>(v);     // quad_perm [1, 0, 3, 2]
+  v = v + dpp<0x4E>(v);     // quad_perm [2, 3, 0, 1]
+  v = v + dpp<0x141>(v);    // row_half_mirror
+  v = v + dpp<0x140>(v);    // row_mirror
+  if constexpr (NR == 32) {
+    const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+  }
+  return v;
 }
 
 __device__ __forceinline__ void coll_resid3(float rx, float ry, float rz, float ia2, float ib2, float b,
@@ -182,7 +223,11 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
   const int64_t ckpt_stride = A.ckpt_stride;
   constexpr int NR = 16 * R;
   constexpr int PR = (NR * (NR - 1) / 2 + 63) / 64;   // 64-pair rounds of the broad phase
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int MFX = kQPRow;                         // free coefficients per robot-axis (<= 10), padded
+  constexpr int TAILW = (3 * NR + 63) / 64;           // waves running the multiplier and QP steps
+  static_assert(TAILW <= W, "the multiplier/QP step needs 3 x 16R lanes");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col = lane & 15, grp = lane >> 4;
   const int nthr = 64 * W;
   {
@@ -191,11 +236,10 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
     const DevCfg c = cfgs[pr.cfg];
     const FastLds L = fast_lds_plan(c, R, W);
     const int n = c.n, m = c.m, mf = c.mf, H = c.H;
-    const int nDm = n * 3 * m, nDf = n * 3 * mf, nD6 = n * 3 * kNFix;
+    const int nDm = n * 3 * m, nDf = n * 3 * mf;
     const int Np = n * (n - 1) / 2;
     const int NT = (H + 15) / 16;
     const int TQ = (NT + W - 1) / W;            // time tiles per wave
-    const float* basis = tab + c.off_basis;
     const float* X1 = tab + c.off_X1;
     const float* X01 = tab + c.off_X01;
     const float* Bmap = tab + c.off_Bmap;
@@ -204,44 +248,47 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
     const float ia2 = (float)c.inv_a2, ib2 = (float)c.inv_b2, sb = (float)c.b;
     const float vmax = (float)c.vmax, amax = (float)c.amax;
     const float n_rho_c = (float)c.n_rho_c, inv_n = 1.0f / (float)n;
+    const float Lv = (float)c.lip_v, La = (float)c.lip_a;
     const float* bv = bvals + pr.bnd_off;
     float* sxi = smem + L.xi;
     float* slam = smem + L.lam;
     float* sxb = smem + L.xb;
     float* sxprev = smem + L.xprev;
-    float* sxp = smem + L.xp;
-    float* sdlt = smem + L.dlt;
     float* sdbar = smem + L.dbar;
     float* scorr = smem + L.corr;
-    float* sybuf = smem + L.ybuf;
-    float* sybar = smem + L.ybar;
     int* spairs = reinterpret_cast<int*>(smem + L.pairs);
-    float* sred = smem + L.red;
-    // bound-ball drift tracking (see the velocity/acceleration section of the tile loop)
-    float* s_mv = smem + L.ball;             // margin of the velocity bound at the last evaluation
-    float* s_dv = s_mv + NR;                 // accumulated bound on the velocity drift since then
-    float* s_ma = s_dv + NR;
-    float* s_da = s_ma + NR;
-    unsigned* s_vmx = reinterpret_cast<unsigned*>(s_da + NR);   // max ||v||^2 (float bits) this iteration
-    unsigned* s_amx = s_vmx + NR;
-    unsigned* s_dxi = s_amx + NR;            // max |change of a free coefficient| per (robot, axis)
-    int* s_flag = reinterpret_cast<int*>(s_dxi + 3 * NR);
-    const float Lv = (float)c.lip_v, La = (float)c.lip_a;
+    float* s_vmx = smem + L.vmx;
+    float* s_amx = smem + L.amx;
+    float* s_dxi = smem + L.dxi;
     float* wbuf = smem + L.tiles + wave * L.per_wave;
     float* Xt = wbuf + L.xt;
     float* Ct = wbuf + L.ct;
     float* bb = wbuf + L.bb;
     int* plist = reinterpret_cast<int*>(wbuf + L.plist);
-    float* gpart = smem + L.gpart;
+    // pinned coefficient r of a robot-axis row after the first step: Bmap (p0, v0, a0, pH, vH, aH)
+    auto pinned = [&](int row, int r) {
+      float acc = 0.0f;
+      for (int s = 0; s < kNFix; ++s) acc = fmaf(Bmap[r * kNFix + s], bv[row * kNFix + s], acc);
+      return acc;
+    };
+    auto fixed_k = [&](int r) { return r < 3 ? r : m - kNFix + r; };
 
     // pair table, lexicographic (i, j), i < j
     for (int i = tid; i < n; i += nthr) {
       int p = i * n - i * (i + 1) / 2;
       for (int j = i + 1; j < n; ++j) spairs[p++] = i | (j << 8);
     }
-    // loop-invariant MFMA A operands of this wave's tiles (basis rows of S1)
+    // QP matrices X1 (relative motion) and X01 (mean motion minus relative), zero-padded rows
+    float* sX1 = smem + L.qp;
+    float* sX01 = sX1 + mf * kQPRow;
+    for (int q = tid; q < 2 * mf * kQPRow; q += nthr) {
+      const int mat = q / (mf * kQPRow), rem = q - mat * mf * kQPRow;
+      const int f = rem / kQPRow, f2 = rem - f * kQPRow;
+      sX1[q] = f2 < mf ? (mat == 0 ? X1 : X01)[f * mf + f2] : 0.0f;
+    }
+    // basis operand tables: fp32 [tile][basis][S1 A operand, S4 B operand (x rho)][lane],
+    // 16-bit [tile][basis][instruction][lane]
     const float4* a32c = reinterpret_cast<const float4*>(a16) + c.off_a32;
-    const float rho[3] = {(float)c.rho_c, (float)c.rho_v, (float)c.rho_a};
     const uint4* a16c = a16 + (MP == 1 ? c.off_a16[0] : c.off_a16[1]);
     __syncthreads();
     int mypair[PR];
@@ -257,29 +304,14 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         sxi[q] = xi0 ? xi0[coef + q] : x;
         slam[q] = lam0 ? lam0[coef + q] : 0.0f;
       }
-      for (int q = tid; q < nD6; q += nthr) {
-        const int row = q / kNFix, r = q - row * kNFix;
-        float acc = 0.0f;
-        for (int s = 0; s < kNFix; ++s) acc = fmaf(Bmap[r * kNFix + s], bv[row * kNFix + s], acc);
-        sxp[q] = acc;
-      }
-      for (int q = tid; q < NR; q += nthr) {
-        s_mv[q] = -1.0f; s_dv[q] = 0.0f; s_ma[q] = -1.0f; s_da[q] = 0.0f;
-        s_vmx[q] = 0u; s_amx[q] = 0u;
-        s_dxi[3 * q] = s_dxi[3 * q + 1] = s_dxi[3 * q + 2] = 0u;
-      }
-      if (tid == 0) s_flag[0] = 0;
+      for (int q = tid; q < 3 * NR; q += nthr) s_dxi[q] = 0.0f;
       __syncthreads();
-      for (int q = tid; q < nD6; q += nthr) {
-        const int row = q / kNFix, r = q - row * kNFix;
-        const int k = r < 3 ? r : m - kNFix + r;
-        sdlt[q] = sxi[row * m + k] - sxp[q];
-      }
-      __syncthreads();
+      // the first QP step also moves the pinned coefficients (from xi0 to their boundary values);
+      // its effect on the free ones is the correction G_rho (xi0 - xi_p) restricted to them
       for (int q = tid; q < 3 * kNFix; q += nthr) {
         const int d = q / kNFix, r = q - d * kNFix;
         float s = 0.0f;
-        for (int i = 0; i < n; ++i) s += sdlt[(i * 3 + d) * kNFix + r];
+        for (int i = 0; i < n; ++i) s += sxi[(i * 3 + d) * m + fixed_k(r)] - pinned(i * 3 + d, r);
         sdbar[q] = s * inv_n;
       }
       __syncthreads();
@@ -287,15 +319,28 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         const int row = q / mf, f = q - row * mf, d = row % 3;
         float acc = 0.0f;
         for (int r = 0; r < kNFix; ++r) {
-          const float dl = sdlt[row * kNFix + r];
+          const float dl = sxi[row * m + fixed_k(r)] - pinned(row, r);
           acc = fmaf(n_rho_c * Gfx[f * kNFix + r], dl - sdbar[d * kNFix + r], acc);
           acc = fmaf(Rfx[f * kNFix + r], dl, acc);
         }
         scorr[q] = acc;
       }
       __syncthreads();
+      // bound-ball drift tracking, lane = robot, identical in every wave: margin to the bound at
+      // the last evaluation and accumulated bound on the drift since then
+      float mv = -1.0f, dv = 0.0f, ma = -1.0f, da = 0.0f;
 
       for (int k = 0; k < iters; ++k) {
+        // Lane-dependent indices are re-derived from an opaque copy every iteration: otherwise the
+        // compiler hoists every per-lane address of the loop body out of the sample loop and
+        // spills them.
+        int lane_o = tid;
+        asm volatile("" : "+v"(lane_o));
+        const int tid = lane_o, lane = lane_o & 63;
+        const int col = lane & 15, grp = lane >> 4;
+        const int t_ax = tid / NR, t_rb = tid - t_ax * NR;
+        const bool t_on = tid < 3 * NR && t_rb < n;
+        const int t_row = t_rb * 3 + t_ax;
         if (ckpt && (k % ckpt_every) == 0) {
           const int64_t base = (int64_t)(k / ckpt_every) * 2 * ckpt_stride + coef;
           for (int q = tid; q < nDm; q += nthr) {
@@ -310,21 +355,19 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         // below its margin to the bound at the last evaluation, the ball residuals are exactly zero
         // and S1/S3/S4 for that basis are skipped.  Iterations 0 and 1 always evaluate (the pinned
         // coefficients change in the first step).
-        for (int q = tid; q < n; q += nthr) {
-          const float d0 = __uint_as_float(s_dxi[3 * q]), d1 = __uint_as_float(s_dxi[3 * q + 1]);
-          const float d2 = __uint_as_float(s_dxi[3 * q + 2]);
-          const float dn = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
-          s_dxi[3 * q] = s_dxi[3 * q + 1] = s_dxi[3 * q + 2] = 0u;
-          const float dv = s_dv[q] + Lv * dn, da = s_da[q] + La * dn;
-          s_dv[q] = dv;
-          s_da[q] = da;
-          int f = 0;
-          if (c.vel_on && dv >= s_mv[q] - 1e-4f * vmax) f |= 1;
-          if (c.acc_on && da >= s_ma[q] - 1e-4f * amax) f |= 2;
-          if (f) atomicOr(s_flag, f);
+        int eval_flags = 3;
+        {
+          float dn = 0.0f;
+          if (lane < n) {
+            const float d0 = s_dxi[lane * 3], d1 = s_dxi[lane * 3 + 1], d2 = s_dxi[lane * 3 + 2];
+            dn = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+          }
+          dv += Lv * dn;
+          da += La * dn;
+          const bool fv = c.vel_on && lane < n && dv >= mv - 1e-4f * vmax;
+          const bool fa = c.acc_on && lane < n && da >= ma - 1e-4f * amax;
+          if (k >= 2) eval_flags = (ballot(fv) != 0 ? 1 : 0) | (ballot(fa) != 0 ? 2 : 0);
         }
-        __syncthreads();
-        const int eval_flags = (k < 2) ? 3 : s_flag[0];
         // S1 B operand: xi^T, lane (col, grp) holds robot col, coefficient 4 s + grp
         float bx[MP == 0 ? R : 1][3][KS];
         typename Half<MP == 0 ? 1 : MP>::V hb1[MP == 0 ? 1 : R][3], hb2[MP == 0 ? 1 : R][3];
@@ -344,25 +387,24 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
 #pragma unroll
             for (int d = 0; d < 3; ++d) split_xi<MP>(sxi, 16 * rr + col, n, m, d, grp, hb1[rr][d], hb2[rr][d]);
         }
-        // S1 product for basis b of tile q: Y[rr][d] (lane (col, grp): robot col, times 4 grp + r)
-        auto s1 = [&](int q, int tau, int b, f4 (&Y)[R][3]) {
-          if constexpr (MP == 0) {
-            const float4 av = a32c[(tau * 3 + b) * 64 + lane];
-            const float a1[4] = {av.x, av.y, av.z, av.w};
+        // S1 product for one basis of one tile: Y[rr][d] (lane (col, grp): robot col, times 4 grp + r)
+        auto s1_32 = [&](const float4 av, f4 (&Y)[R][3]) {
+          const float a1[4] = {av.x, av.y, av.z, av.w};
 #pragma unroll
-            for (int rr = 0; rr < R; ++rr)
+          for (int rr = 0; rr < R; ++rr)
 #pragma unroll
-              for (int d = 0; d < 3; ++d) {
-                f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int d = 0; d < 3; ++d) {
+              f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                for (int s = 0; s < KS; ++s) acc = mfma4(a1[s], bx[rr][d][s], acc);
-                Y[rr][d] = acc;
-              }
-          } else {
+              for (int s = 0; s < KS; ++s) acc = mfma4(a1[s], bx[rr][d][s], acc);
+              Y[rr][d] = acc;
+            }
+        };
+        auto s1_16 = [&](const uint4 u1, const uint4 u2, f4 (&Y)[R][3]) {
+          if constexpr (MP != 0) {
             typedef typename Half<MP>::V V;
-            const uint4* at = a16c + ((tau * 3 + b) * 2) * 64 + lane;
-            const V A1 = __builtin_bit_cast(V, at[0]);
-            const V A2 = __builtin_bit_cast(V, at[64]);
+            const V A1 = __builtin_bit_cast(V, u1);
+            const V A2 = __builtin_bit_cast(V, u2);
 #pragma unroll
             for (int rr = 0; rr < R; ++rr)
 #pragma unroll
@@ -379,6 +421,20 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         for (int rr = 0; rr < R; ++rr)
 #pragma unroll
           for (int d = 0; d < 3; ++d) gacc[rr][d] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        float vm[2][R];           // max ||v||^2, ||a||^2 of robot col over this wave's tiles
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) vm[0][rr] = vm[1][rr] = 0.0f;
+        // position operands of the wave's first tile; each tile prefetches those of its next one
+        float4 pa = {0.0f, 0.0f, 0.0f, 0.0f}, pb = {0.0f, 0.0f, 0.0f, 0.0f};
+        uint4 pu1 = {0u, 0u, 0u, 0u}, pu2 = {0u, 0u, 0u, 0u};
+        if (wave < NT) {
+          if constexpr (MP == 0) pa = a32c[((wave * 3) * 2) * 64 + lane];
+          else {
+            pu1 = a16c[((wave * 3) * 2) * 64 + lane];
+            pu2 = a16c[((wave * 3) * 2 + 1) * 64 + lane];
+          }
+          pb = a32c[((wave * 3) * 2 + 1) * 64 + lane];
+        }
 
 #pragma unroll 1
         for (int q = 0; q < TQ; ++q) {
@@ -386,15 +442,27 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           if (tau >= NT) break;
           const int t0 = 16 * tau;
           const int nt = min(16, H - t0);
+          const float4 ca = pa, cb = pb;
+          const uint4 cu1 = pu1, cu2 = pu2;
+          if (tau + W < NT) {
+            const int nx = tau + W;
+            if constexpr (MP == 0) pa = a32c[((nx * 3) * 2) * 64 + lane];
+            else {
+              pu1 = a16c[((nx * 3) * 2) * 64 + lane];
+              pu2 = a16c[((nx * 3) * 2 + 1) * 64 + lane];
+            }
+            pb = a32c[((nx * 3) * 2 + 1) * 64 + lane];
+          }
           // ---- S1 positions -> LDS, per-robot boxes over the tile in registers ----
           {
             f4 Y[R][3];
-            s1(q, tau, 0, Y);
+            if constexpr (MP == 0) s1_32(ca, Y);
+            else s1_16(cu1, cu2, Y);
 #pragma unroll
             for (int rr = 0; rr < R; ++rr)
 #pragma unroll
               for (int d = 0; d < 3; ++d) {
-                const int o = (d * NR + 16 * rr + col) * kRS + 4 * grp;
+                const int o = tile_at(d * NR + 16 * rr + col, 4 * grp);
                 *reinterpret_cast<f4*>(Xt + o) = Y[rr][d];
                 *reinterpret_cast<f4*>(Ct + o) = f4{0.0f, 0.0f, 0.0f, 0.0f};
               }
@@ -411,10 +479,8 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                     lo[d] = fminf(lo[d], Y[rr][d][r]);
                     hi[d] = fmaxf(hi[d], Y[rr][d][r]);
                   }
-                lo[d] = fminf(lo[d], __shfl_xor(lo[d], 16));
-                hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], 16));
-                lo[d] = fminf(lo[d], __shfl_xor(lo[d], 32));
-                hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], 32));
+                lo[d] = grp_min(lo[d]);
+                hi[d] = grp_max(hi[d]);
               }
               if (grp == 0) {
                 float* bq = bb + (16 * rr + col) * 8;
@@ -430,9 +496,9 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             if (!on || !(eval_flags & b)) continue;
             const float lim = b == 1 ? vmax : amax;
             f4 Y[R][3];
-            s1(q, tau, b, Y);
+            if constexpr (MP == 0) s1_32(a32c[((tau * 3 + b) * 2) * 64 + lane], Y);
+            else s1_16(a16c[((tau * 3 + b) * 2) * 64 + lane], a16c[((tau * 3 + b) * 2 + 1) * 64 + lane], Y);
             bool nz = false;
-            unsigned* smx = b == 1 ? s_vmx : s_amx;
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
               float mx = 0.0f;
@@ -447,17 +513,11 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                 Y[rr][2][r] = f * vz;
                 nz |= f != 0.0f;
               }
-              mx = fmaxf(mx, __shfl_xor(mx, 16));
-              mx = fmaxf(mx, __shfl_xor(mx, 32));
-              if (grp == 0 && 16 * rr + col < n) atomicMax(smx + 16 * rr + col, __float_as_uint(mx));
+              vm[b - 1][rr] = fmaxf(vm[b - 1][rr], grp_max(mx));
             }
             if (ballot(nz) != 0) {
-              float b4[4];
-#pragma unroll
-              for (int s = 0; s < 4; ++s) {
-                const int t = t0 + 4 * grp + s;
-                b4[s] = (t < H && col < m) ? rho[b] * basis[((size_t)b * H + t) * m + col] : 0.0f;
-              }
+              const float4 bq = a32c[((tau * 3 + b) * 2 + 1) * 64 + lane];
+              const float b4[4] = {bq.x, bq.y, bq.z, bq.w};
 #pragma unroll
               for (int rr = 0; rr < R; ++rr)
 #pragma unroll
@@ -475,10 +535,14 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             bool act = false;
             if (pij >= 0) {
               const int i = pij & 255, j = pij >> 8;
+              const f4 li = *reinterpret_cast<const f4*>(bb + i * 8);
+              const f4 hi = *reinterpret_cast<const f4*>(bb + i * 8 + 4);
+              const f4 lj = *reinterpret_cast<const f4*>(bb + j * 8);
+              const f4 hj = *reinterpret_cast<const f4*>(bb + j * 8 + 4);
               float g2 = 0.0f;
 #pragma unroll
               for (int d = 0; d < 3; ++d) {
-                const float gap = fmaxf(0.0f, fmaxf(bb[j * 8 + d] - bb[i * 8 + 4 + d], bb[i * 8 + d] - bb[j * 8 + 4 + d]));
+                const float gap = fmaxf(0.0f, fmaxf(lj[d] - hi[d], li[d] - hj[d]));
                 g2 += gap * gap * (d == 2 ? ib2 : ia2);
               }
               act = g2 < 1.0001f;
@@ -494,45 +558,39 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             if (slot < count && col < nt) {
               const int pij = plist[slot];
               const int i = pij & 255, j = pij >> 8;
-              const float rx = Xt[(0 * NR + i) * kRS + col] - Xt[(0 * NR + j) * kRS + col];
-              const float ry = Xt[(1 * NR + i) * kRS + col] - Xt[(1 * NR + j) * kRS + col];
-              const float rz = Xt[(2 * NR + i) * kRS + col] - Xt[(2 * NR + j) * kRS + col];
+              const float rx = Xt[tile_at(0 * NR + i, col)] - Xt[tile_at(0 * NR + j, col)];
+              const float ry = Xt[tile_at(1 * NR + i, col)] - Xt[tile_at(1 * NR + j, col)];
+              const float rz = Xt[tile_at(2 * NR + i, col)] - Xt[tile_at(2 * NR + j, col)];
               float Rx, Ry, Rz;
               coll_resid3(rx, ry, rz, ia2, ib2, sb, Rx, Ry, Rz);
               if (Rx != 0.0f || Ry != 0.0f || Rz != 0.0f) {
                 nzc = true;
-                atomicAdd(Ct + (0 * NR + i) * kRS + col, Rx);
-                atomicAdd(Ct + (1 * NR + i) * kRS + col, Ry);
-                atomicAdd(Ct + (2 * NR + i) * kRS + col, Rz);
-                atomicAdd(Ct + (0 * NR + j) * kRS + col, -Rx);
-                atomicAdd(Ct + (1 * NR + j) * kRS + col, -Ry);
-                atomicAdd(Ct + (2 * NR + j) * kRS + col, -Rz);
+                atomicAdd(Ct + tile_at(0 * NR + i, col), Rx);
+                atomicAdd(Ct + tile_at(1 * NR + i, col), Ry);
+                atomicAdd(Ct + tile_at(2 * NR + i, col), Rz);
+                atomicAdd(Ct + tile_at(0 * NR + j, col), -Rx);
+                atomicAdd(Ct + tile_at(1 * NR + j, col), -Ry);
+                atomicAdd(Ct + tile_at(2 * NR + j, col), -Rz);
               }
             }
           }
           if (ballot(nzc) != 0) {
             wave_sync();
-            float b4[4];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-              const int t = t0 + 4 * grp + s;
-              b4[s] = (t < H && col < m) ? rho[0] * basis[(size_t)t * m + col] : 0.0f;
-            }
+            const float b4[4] = {cb.x, cb.y, cb.z, cb.w};
 #pragma unroll
             for (int rr = 0; rr < R; ++rr)
 #pragma unroll
               for (int d = 0; d < 3; ++d) {
-                const f4 cr = *reinterpret_cast<const f4*>(Ct + (d * NR + 16 * rr + col) * kRS + 4 * grp);
+                const f4 cr = *reinterpret_cast<const f4*>(Ct + tile_at(d * NR + 16 * rr + col, 4 * grp));
 #pragma unroll
                 for (int s = 0; s < 4; ++s) gacc[rr][d] = mfma4(cr[s], b4[s], gacc[rr][d]);
               }
           }
           wave_sync();
         }
-        // partial back-projection of this wave -> LDS (aliases the tile buffers)
-        __syncthreads();
+        // this wave's partial back-projection and bound maxima -> its own LDS region
         {
-          float* gp = gpart + wave * nDm;
+          float* gp = wbuf;
 #pragma unroll
           for (int rr = 0; rr < R; ++rr)
 #pragma unroll
@@ -542,58 +600,108 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                 const int robot = 16 * rr + 4 * grp + r;
                 if (robot < n && col < m) gp[(robot * 3 + d) * m + col] = gacc[rr][d][r];
               }
+          if (grp == 0) {
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+              if (eval_flags & 1) s_vmx[wave * NR + 16 * rr + col] = vm[0][rr];
+              if (eval_flags & 2) s_amx[wave * NR + 16 * rr + col] = vm[1][rr];
+            }
+          }
         }
         __syncthreads();
-        for (int q = tid; q < n; q += nthr) {
+        // margins to the bounds after an evaluating iteration (every wave, identical values)
+        if (lane < n) {
           if (eval_flags & 1) {
-            s_mv[q] = vmax - sqrtf(__uint_as_float(s_vmx[q]));
-            s_dv[q] = 0.0f;
-            s_vmx[q] = 0u;
+            float mx = 0.0f;
+            for (int ww = 0; ww < W; ++ww) mx = fmaxf(mx, s_vmx[ww * NR + lane]);
+            mv = vmax - sqrtf(mx);
+            dv = 0.0f;
           }
           if (eval_flags & 2) {
-            s_ma[q] = amax - sqrtf(__uint_as_float(s_amx[q]));
-            s_da[q] = 0.0f;
-            s_amx[q] = 0u;
+            float mx = 0.0f;
+            for (int ww = 0; ww < W; ++ww) mx = fmaxf(mx, s_amx[ww * NR + lane]);
+            ma = amax - sqrtf(mx);
+            da = 0.0f;
           }
         }
-        if (tid == 0) s_flag[0] = 0;
-        // multiplier step and QP step on the free coefficients
-        for (int q = tid; q < nDm; q += nthr) {
-          float gq = 0.0f;
+        // multiplier step (all coefficients) and QP step (free coefficients) of row (robot, axis),
+        // owned by thread 16R * axis + robot:
+        // g = F^T rho R summed over the waves, lambda <- lambda - g,
+        // y = xi_bar - xi + lambda - g (+ the first-step correction), and
+        // xi_free += X1 y + X01 mean_robots(y)
+        const float* gp0 = smem + L.tiles;
+        auto gsum = [&](int q) {
+          float g = 0.0f;
 #pragma unroll
-          for (int ww = 0; ww < W; ++ww) gq += gpart[ww * nDm + q];
-          const float ln = slam[q] - gq;
-          slam[q] = ln;
-          const int row = q / m, kk = q - row * m, f = kk - 3;
-          if (f >= 0 && f < mf) {
-            float y = sxb[q] - sxi[q] + ln - gq;
-            if (k == 0) y += scorr[row * mf + f];
-            sybuf[row * mf + f] = y;
-          }
-        }
-        __syncthreads();
-        for (int q = tid; q < 3 * mf; q += nthr) {
-          const int d = q / mf, f = q - d * mf;
-          float s = 0.0f;
-          for (int i = 0; i < n; ++i) s += sybuf[(i * 3 + d) * mf + f];
-          sybar[q] = s * inv_n;
-        }
-        __syncthreads();
-        for (int q = tid; q < nDf; q += nthr) {
-          const int row = q / mf, f = q - row * mf, d = row % 3;
-          float acc = 0.0f;
-          for (int f2 = 0; f2 < mf; ++f2) {
-            acc = fmaf(X1[f * mf + f2], sybuf[row * mf + f2], acc);
-            acc = fmaf(X01[f * mf + f2], sybar[d * mf + f2], acc);
-          }
-          sxi[row * m + 3 + f] += acc;
-          atomicMax(s_dxi + row, __float_as_uint(fabsf(acc)));
-        }
-        if (k == 0) {
-          for (int q = tid; q < nD6; q += nthr) {
+          for (int ww = 0; ww < W; ++ww) g += gp0[ww * L.per_wave + q];
+          return g;
+        };
+        // pinned coefficients: multiplier step only (and their boundary values in the first step),
+        // on the waves that do not run the QP step when there are any
+        if (W == TAILW || wave >= TAILW) {
+          constexpr int base = W > TAILW ? 64 * TAILW : 0;
+          for (int q = tid - base; q < n * 3 * kNFix; q += nthr - base) {
             const int row = q / kNFix, r = q - row * kNFix;
-            const int kk = r < 3 ? r : m - kNFix + r;
-            sxi[row * m + kk] = sxp[q];
+            const int qq = row * m + fixed_k(r);
+            slam[qq] = slam[qq] - gsum(qq);
+            if (k == 0) sxi[qq] = pinned(row, r);
+          }
+        }
+        if (wave < TAILW) {
+          float y[MFX];
+#pragma unroll
+          for (int f = 0; f < MFX; ++f) y[f] = 0.0f;
+          if (t_on) {
+            float gv[MFX], lv[MFX], bv_[MFX], xv[MFX], cv[MFX];
+#pragma unroll
+            for (int f = 0; f < MFX; ++f) {
+              gv[f] = lv[f] = bv_[f] = xv[f] = cv[f] = 0.0f;
+              if (f < mf) {
+                const int q = t_row * m + 3 + f;
+                gv[f] = gsum(q);
+                lv[f] = slam[q];
+                bv_[f] = sxb[q];
+                xv[f] = sxi[q];
+                if (k == 0) cv[f] = scorr[t_row * mf + f];
+              }
+            }
+#pragma unroll
+            for (int f = 0; f < MFX; ++f) {
+              if (f < mf) {
+                const float ln = lv[f] - gv[f];
+                slam[t_row * m + 3 + f] = ln;
+                float yv = bv_[f] - xv[f] + ln - gv[f];
+                if (k == 0) yv += cv[f];
+                y[f] = yv;
+              }
+            }
+          }
+          float yb[MFX];
+#pragma unroll
+          for (int f = 0; f < MFX; ++f) yb[f] = f < mf ? group_sum<NR>(y[f]) * inv_n : 0.0f;
+          if (t_on) {
+            float dmax = 0.0f;
+#pragma unroll
+            for (int f = 0; f < MFX; ++f) {
+              if (f < mf) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int cc = 0; cc < MFX / 4; ++cc) {
+                  if (4 * cc < mf) {
+                    const f4 a = *reinterpret_cast<const f4*>(sX1 + f * kQPRow + 4 * cc);
+                    const f4 b = *reinterpret_cast<const f4*>(sX01 + f * kQPRow + 4 * cc);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                      acc = fmaf(a[j], y[4 * cc + j], acc);
+                      acc = fmaf(b[j], yb[4 * cc + j], acc);
+                    }
+                  }
+                }
+                sxi[t_row * m + 3 + f] += acc;
+                dmax = fmaxf(dmax, fabsf(acc));
+              }
+            }
+            s_dxi[t_row] = dmax;
           }
         }
         __syncthreads();
@@ -637,7 +745,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             for (int b = 0; b < 3; ++b) {
               f4 Yp[R][3], Yn[R][3];
               if constexpr (MP == 0) {
-                const float4 av = a32c[(tau * 3 + b) * 64 + lane];
+                const float4 av = a32c[((tau * 3 + b) * 2) * 64 + lane];
                 const float a1[4] = {av.x, av.y, av.z, av.w};
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr)
@@ -675,7 +783,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                 for (int rr = 0; rr < R; ++rr)
 #pragma unroll
                   for (int d = 0; d < 3; ++d) {
-                    const int o = (d * NR + 16 * rr + col) * kRS + 4 * grp;
+                    const int o = tile_at(d * NR + 16 * rr + col, 4 * grp);
                     *reinterpret_cast<f4*>(Xt + o) = Yp[rr][d];
                     *reinterpret_cast<f4*>(Ct + o) = Yn[rr][d];
                   }
@@ -709,8 +817,8 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                 float rp[3], rn[3];
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                  rp[d] = Xt[(d * NR + i) * kRS + col] - Xt[(d * NR + j) * kRS + col];
-                  rn[d] = Ct[(d * NR + i) * kRS + col] - Ct[(d * NR + j) * kRS + col];
+                  rp[d] = Xt[tile_at(d * NR + i, col)] - Xt[tile_at(d * NR + j, col)];
+                  rn[d] = Ct[tile_at(d * NR + i, col)] - Ct[tile_at(d * NR + j, col)];
                 }
                 float Rx, Ry, Rz;
                 coll_resid3(rp[0], rp[1], rp[2], ia2, ib2, sb, Rx, Ry, Rz);
@@ -723,14 +831,18 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             wave_sync();
           }
         }
-        sred[tid] = ss;
-        sred[nthr + tid] = mx;
+        // per-wave partial sums in the wave's own region, combined in thread order
+        wbuf[lane] = ss;
+        wbuf[64 + lane] = mx;
         __syncthreads();
         if (tid == 0) {
           float s = 0.0f, mm = 0.0f;
-          for (int q = 0; q < nthr; ++q) {
-            s += sred[q];
-            mm = fmaxf(mm, sred[nthr + q]);
+          for (int ww = 0; ww < W; ++ww) {
+            const float* rw = smem + L.tiles + ww * L.per_wave;
+            for (int l = 0; l < 64; ++l) {
+              s += rw[l];
+              mm = fmaxf(mm, rw[64 + l]);
+            }
           }
           resid_out[sidx * 2 + 0] = s;
           resid_out[sidx * 2 + 1] = sqrtf(mm);
@@ -765,7 +877,7 @@ fast_batched_kernel(FastArgs A, int* __restrict__ queue) {
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(queue, 1);
     __syncthreads();
-    const int it = next;
+    const int it = __builtin_amdgcn_readfirstlane(next);
     __syncthreads();
     if (it >= A.n_items) break;
     const int n = A.cfgs[A.probs[A.items[it].problem].cfg].n;
@@ -839,18 +951,22 @@ float f16_value(uint16_t b) {
 
 }  // namespace
 
-int64_t a32_entries(const DevCfg& c) { return (int64_t)((c.H + 15) / 16) * 3 * 64; }
+int64_t a32_entries(const DevCfg& c) { return (int64_t)((c.H + 15) / 16) * 3 * 2 * 64; }
 
 void a32_fill(const DevCfg& c, const double* P3, float* out) {
   const int NT = (c.H + 15) / 16;
+  const double rho[3] = {c.rho_c, c.rho_v, c.rho_a};
   for (int tau = 0; tau < NT; ++tau)
     for (int b = 0; b < 3; ++b)
       for (int lane = 0; lane < 64; ++lane) {
-        const int col = lane & 15, grp = lane >> 4, t = 16 * tau + col;
+        const int col = lane & 15, grp = lane >> 4;
+        float* a = out + ((((size_t)tau * 3 + b) * 2 + 0) * 64 + lane) * 4;   // S1: P[t = 16 tau + col][k = 4 s + grp]
+        float* bq = out + ((((size_t)tau * 3 + b) * 2 + 1) * 64 + lane) * 4;  // S4: rho P[t = 16 tau + 4 grp + s][k = col]
         for (int s = 0; s < 4; ++s) {
-          const int k = 4 * s + grp;
-          out[(((size_t)tau * 3 + b) * 64 + lane) * 4 + s] =
-              (t < c.H && k < c.m) ? (float)P3[((size_t)b * c.H + t) * c.m + k] : 0.0f;
+          const int t = 16 * tau + col, k = 4 * s + grp;
+          a[s] = (t < c.H && k < c.m) ? (float)P3[((size_t)b * c.H + t) * c.m + k] : 0.0f;
+          const int t4 = 16 * tau + 4 * grp + s;
+          bq[s] = (t4 < c.H && col < c.m) ? (float)(rho[b] * P3[((size_t)b * c.H + t4) * c.m + col]) : 0.0f;
         }
       }
 }
@@ -920,13 +1036,17 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     out.ncu = ncu > 0 ? ncu : 256;
-    auto slots = [&](int W) {
-      const int by_waves = (4 * waves_per_simd(out.batched ? 2 : out.R, 0)) / W;
+    // resident work items at W waves per workgroup for the register budget of each precision
+    auto slots = [&](int W, int mp) {
+      const int by_waves = (4 * waves_per_simd(out.batched ? 2 : out.R, mp)) / W;
       const int by_lds = (int)((160 * 1024) / std::max<size_t>(out.lds_bytes_w[W / 2 - 1], 1));
       return (int64_t)std::max(1, std::min(by_waves, by_lds)) * out.ncu;
     };
     const int64_t ni = (int64_t)items.size();
-    out.W = (ni > slots(4) && ni <= slots(2)) ? 2 : 4;
+    for (int prec = SF_FP32; prec <= SF_FP16; ++prec) {
+      const int mp = prec - SF_FP32;
+      out.Wp[prec & 3] = (ni > slots(4, mp) && ni <= slots(2, mp)) ? 2 : 4;
+    }
   }
   if (out.batched) {
     // longest-processing-time order: most expensive work items first
@@ -948,7 +1068,8 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
       g_fast_err = "persistent plan allocation failed";
       return SF_ENOMEM;
     }
-    const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(out.lds_bytes_w[out.W / 2 - 1], 1))));
+    const int wdef = out.Wp[SF_FP32 & 3];
+    const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(out.lds_bytes_w[wdef / 2 - 1], 1))));
     out.grid = std::min<int>((int)items.size(), out.ncu * per_cu);
   }
   out.ok = true;
@@ -1031,7 +1152,7 @@ hipError_t launch_mp(const FastPlan& p, const LaunchArgs& a, const float* tab32,
 }
 
 hipError_t fast_launch(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16, int precision) {
-  const int W = p.tuned_w[precision & 3] > 0 ? p.tuned_w[precision & 3] : p.W;
+  const int W = p.tuned_w[precision & 3] > 0 ? p.tuned_w[precision & 3] : p.Wp[precision & 3];
   if (p.batched) {
     const int g = p.tuned_grid[precision & 3] > 0 ? p.tuned_grid[precision & 3] : p.grid;
     return fast_launch_batched(p, a, tab32, a16, precision, g, W);
