@@ -15,7 +15,7 @@ struct FastPlan {
   int KS = 0;                   // k-steps of 4 coefficients (maximum over the batch)
   int Wp[4] = {4, 4, 4, 4};     // default waves per workgroup (2 or 4) per precision; time tiles
                                 // are dealt round-robin to the waves
-  size_t lds_bytes_w[2] = {0, 0};       // LDS per workgroup for W = 2 and W = 4
+  size_t lds_bytes[2][3] = {};          // LDS per workgroup for W = 2, 4 and fp32 / bf16 / fp16
   // persistent launch over a ragged batch (mixed swarm sizes, or requested)
   bool batched = false;
   WorkItem* d_items_sorted = nullptr;   // work items, most expensive first

@@ -91,11 +91,11 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
 // words) and, after the final residual pass, for its partial sums.
 constexpr int kQPRow = 12;               // padded row of the QP matrices in LDS (m_f <= 10)
 struct FastLds {
-  int xi, lam, xb, xprev, dbar, corr, pairs, vmx, amx, dxi, qp, tiles, per_wave, total;
+  int xi, lam, xb, xprev, dbar, corr, pairs, vmx, amx, dxi, qp, hb, tiles, per_wave, total;
   int xt, ct, bb, plist;   // offsets inside one wave's tile region
 };
 
-__host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W) {
+__host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W, int MP) {
   const int nDm = c.n * 3 * c.m, nDf = c.n * 3 * c.mf;
   const int nr = 16 * R, Npmax = nr * (nr - 1) / 2;
   FastLds p;
@@ -112,6 +112,8 @@ __host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W) 
   p.dxi = o; o += 3 * nr;                  // per (robot, axis): max |change| of a free coefficient
   o = (o + 3) & ~3;
   p.qp = o; o += 2 * c.mf * kQPRow;        // X1, X01 with rows padded to kQPRow floats
+  o = (o + 3) & ~3;
+  p.hb = o; o += MP ? 3 * nr * 16 : 0;     // 16-bit S1 B operands: [axis][robot][hi x16, lo x16]
   o = (o + 3) & ~3;                        // 16-byte alignment of the tile buffers
   p.xt = 0;
   p.ct = 3 * nr * 16;
@@ -223,7 +225,9 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
   const int64_t ckpt_stride = A.ckpt_stride;
   constexpr int NR = 16 * R;
   constexpr int PR = (NR * (NR - 1) / 2 + 63) / 64;   // 64-pair rounds of the broad phase
-  constexpr int MFX = kQPRow;                         // free coefficients per robot-axis (<= 10), padded
+  constexpr int MFX = 4 * KS - 6;                     // free coefficients per robot-axis, at most
+  constexpr int MFY = (MFX + 3) & ~3;                 // ... padded to whole 16-byte chunks
+  static_assert(MFY <= kQPRow, "QP rows");
   constexpr int TAILW = (3 * NR + 63) / 64;           // waves running the multiplier and QP steps
   static_assert(TAILW <= W, "the multiplier/QP step needs 3 x 16R lanes");
   const int tid = threadIdx.x, lane = tid & 63;
@@ -234,7 +238,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
     const WorkItem w = items[it];
     const DevProblem pr = probs[w.problem];
     const DevCfg c = cfgs[pr.cfg];
-    const FastLds L = fast_lds_plan(c, R, W);
+    const FastLds L = fast_lds_plan(c, R, W, MP);
     const int n = c.n, m = c.m, mf = c.mf, H = c.H;
     const int nDm = n * 3 * m, nDf = n * 3 * mf;
     const int Np = n * (n - 1) / 2;
@@ -260,6 +264,15 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
     float* s_vmx = smem + L.vmx;
     float* s_amx = smem + L.amx;
     float* s_dxi = smem + L.dxi;
+    // 16-bit hi/lo split of xi in the S1 B-operand layout, kept current by whoever writes xi
+    typedef typename Half<MP == 0 ? 1 : MP>::E HE;
+    HE* shb = reinterpret_cast<HE*>(smem + L.hb);
+    auto put_split = [&](int robot, int d, int kk, float x) {
+      const HE hi = static_cast<HE>(x);
+      const HE lo = static_cast<HE>(x - static_cast<float>(hi));
+      shb[(d * NR + robot) * 32 + kk] = hi;
+      shb[(d * NR + robot) * 32 + 16 + kk] = lo;
+    };
     float* wbuf = smem + L.tiles + wave * L.per_wave;
     float* Xt = wbuf + L.xt;
     float* Ct = wbuf + L.ct;
@@ -278,13 +291,14 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
       int p = i * n - i * (i + 1) / 2;
       for (int j = i + 1; j < n; ++j) spairs[p++] = i | (j << 8);
     }
-    // QP matrices X1 (relative motion) and X01 (mean motion minus relative), zero-padded rows
+    // QP matrices X1 (relative motion) and X01 (mean motion minus relative), stored transposed
+    // (row f2 holds X[f][f2] for all f) with zero-padded rows
     float* sX1 = smem + L.qp;
     float* sX01 = sX1 + mf * kQPRow;
     for (int q = tid; q < 2 * mf * kQPRow; q += nthr) {
       const int mat = q / (mf * kQPRow), rem = q - mat * mf * kQPRow;
-      const int f = rem / kQPRow, f2 = rem - f * kQPRow;
-      sX1[q] = f2 < mf ? (mat == 0 ? X1 : X01)[f * mf + f2] : 0.0f;
+      const int f2 = rem / kQPRow, f = rem - f2 * kQPRow;
+      sX1[q] = f < mf ? (mat == 0 ? X1 : X01)[f * mf + f2] : 0.0f;
     }
     // basis operand tables: fp32 [tile][basis][S1 A operand, S4 B operand (x rho)][lane],
     // 16-bit [tile][basis][instruction][lane]
@@ -305,7 +319,15 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         slam[q] = lam0 ? lam0[coef + q] : 0.0f;
       }
       for (int q = tid; q < 3 * NR; q += nthr) s_dxi[q] = 0.0f;
+      for (int q = lane; q < 3 * NR * 16; q += 64) Ct[q] = 0.0f;
       __syncthreads();
+      if constexpr (MP != 0) {
+        // one thread per (axis, robot, coefficient) of the padded operand rows (zeros outside)
+        for (int q = tid; q < 3 * NR * 16; q += nthr) {
+          const int row = q >> 4, kk = q & 15, d = row / NR, robot = row - d * NR;
+          put_split(robot, d, kk, (robot < n && kk < m) ? sxi[(robot * 3 + d) * m + kk] : 0.0f);
+        }
+      }
       // the first QP step also moves the pinned coefficients (from xi0 to their boundary values);
       // its effect on the free ones is the correction G_rho (xi0 - xi_p) restricted to them
       for (int q = tid; q < 3 * kNFix; q += nthr) {
@@ -329,6 +351,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
       // bound-ball drift tracking, lane = robot, identical in every wave: margin to the bound at
       // the last evaluation and accumulated bound on the drift since then
       float mv = -1.0f, dv = 0.0f, ma = -1.0f, da = 0.0f;
+      int prev_eval = 0;
 
       for (int k = 0; k < iters; ++k) {
         // Lane-dependent indices are re-derived from an opaque copy every iteration: otherwise the
@@ -359,6 +382,22 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         {
           float dn = 0.0f;
           if (lane < n) {
+            // margins to the bounds measured by the previous iteration if it evaluated them
+            // (every wave computes the same values)
+            if (prev_eval & 1) {
+              float mx = 0.0f;
+#pragma unroll
+              for (int ww = 0; ww < W; ++ww) mx = fmaxf(mx, s_vmx[ww * NR + lane]);
+              mv = vmax - sqrtf(mx);
+              dv = 0.0f;
+            }
+            if (prev_eval & 2) {
+              float mx = 0.0f;
+#pragma unroll
+              for (int ww = 0; ww < W; ++ww) mx = fmaxf(mx, s_amx[ww * NR + lane]);
+              ma = amax - sqrtf(mx);
+              da = 0.0f;
+            }
             const float d0 = s_dxi[lane * 3], d1 = s_dxi[lane * 3 + 1], d2 = s_dxi[lane * 3 + 2];
             dn = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
           }
@@ -368,6 +407,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           const bool fa = c.acc_on && lane < n && da >= ma - 1e-4f * amax;
           if (k >= 2) eval_flags = (ballot(fv) != 0 ? 1 : 0) | (ballot(fa) != 0 ? 2 : 0);
         }
+        prev_eval = eval_flags;
         // S1 B operand: xi^T, lane (col, grp) holds robot col, coefficient 4 s + grp
         float bx[MP == 0 ? R : 1][3][KS];
         typename Half<MP == 0 ? 1 : MP>::V hb1[MP == 0 ? 1 : R][3], hb2[MP == 0 ? 1 : R][3];
@@ -382,10 +422,18 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                 bx[rr][d][s] = (robot < n && kk < m) ? sxi[(robot * 3 + d) * m + kk] : 0.0f;
               }
         } else {
+          // lane (col, grp) takes coefficients 8 (grp & 1) .. + 7 of robot col: hi in the first
+          // instruction, lo in the second for grp 0, 1 (zero for grp 2, 3; see split_xi)
+          typedef typename Half<MP == 0 ? 1 : MP>::V V;
 #pragma unroll
           for (int rr = 0; rr < R; ++rr)
 #pragma unroll
-            for (int d = 0; d < 3; ++d) split_xi<MP>(sxi, 16 * rr + col, n, m, d, grp, hb1[rr][d], hb2[rr][d]);
+            for (int d = 0; d < 3; ++d) {
+              const uint4* hrow = reinterpret_cast<const uint4*>(shb + (d * NR + 16 * rr + col) * 32);
+              hb1[rr][d] = __builtin_bit_cast(V, hrow[grp & 1]);
+              const uint4 lo = hrow[2 + (grp & 1)];
+              hb2[rr][d] = __builtin_bit_cast(V, grp < 2 ? lo : uint4{0u, 0u, 0u, 0u});
+            }
         }
         // S1 product for one basis of one tile: Y[rr][d] (lane (col, grp): robot col, times 4 grp + r)
         auto s1_32 = [&](const float4 av, f4 (&Y)[R][3]) {
@@ -462,25 +510,17 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             for (int rr = 0; rr < R; ++rr)
 #pragma unroll
               for (int d = 0; d < 3; ++d) {
-                const int o = tile_at(d * NR + 16 * rr + col, 4 * grp);
-                *reinterpret_cast<f4*>(Xt + o) = Y[rr][d];
-                *reinterpret_cast<f4*>(Ct + o) = f4{0.0f, 0.0f, 0.0f, 0.0f};
+                *reinterpret_cast<f4*>(Xt + tile_at(d * NR + 16 * rr + col, 4 * grp)) = Y[rr][d];
               }
+            // (rows past the horizon repeat the last grid time, so all 16 rows count)
 #pragma unroll
             for (int rr = 0; rr < R; ++rr) {
               float lo[3], hi[3];
 #pragma unroll
               for (int d = 0; d < 3; ++d) {
-                lo[d] = FLT_MAX;
-                hi[d] = -FLT_MAX;
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                  if (4 * grp + r < nt) {
-                    lo[d] = fminf(lo[d], Y[rr][d][r]);
-                    hi[d] = fmaxf(hi[d], Y[rr][d][r]);
-                  }
-                lo[d] = grp_min(lo[d]);
-                hi[d] = grp_max(hi[d]);
+                const f4 v = Y[rr][d];
+                lo[d] = grp_min(fminf(fminf(v[0], v[1]), fminf(v[2], v[3])));
+                hi[d] = grp_max(fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
               }
               if (grp == 0) {
                 float* bq = bb + (16 * rr + col) * 8;
@@ -528,27 +568,30 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           }
           wave_sync();
           // ---- S2: broad phase over the tile, narrow phase on the surviving pairs ----
+          // (unused lanes test the pair (0, 1) and discard the result, so all box loads issue at once)
           int count = 0;
+          bool act[PR];
 #pragma unroll
           for (int r = 0; r < PR; ++r) {
-            const int pij = mypair[r];
-            bool act = false;
-            if (pij >= 0) {
-              const int i = pij & 255, j = pij >> 8;
-              const f4 li = *reinterpret_cast<const f4*>(bb + i * 8);
-              const f4 hi = *reinterpret_cast<const f4*>(bb + i * 8 + 4);
-              const f4 lj = *reinterpret_cast<const f4*>(bb + j * 8);
-              const f4 hj = *reinterpret_cast<const f4*>(bb + j * 8 + 4);
-              float g2 = 0.0f;
+            const int pij = mypair[r] >= 0 ? mypair[r] : (1 << 8);
+            const int i = pij & 255, j = pij >> 8;
+            const f4 li = *reinterpret_cast<const f4*>(bb + i * 8);
+            const f4 hi = *reinterpret_cast<const f4*>(bb + i * 8 + 4);
+            const f4 lj = *reinterpret_cast<const f4*>(bb + j * 8);
+            const f4 hj = *reinterpret_cast<const f4*>(bb + j * 8 + 4);
+            float g2 = 0.0f;
 #pragma unroll
-              for (int d = 0; d < 3; ++d) {
-                const float gap = fmaxf(0.0f, fmaxf(lj[d] - hi[d], li[d] - hj[d]));
-                g2 += gap * gap * (d == 2 ? ib2 : ia2);
-              }
-              act = g2 < 1.0001f;
+            for (int d = 0; d < 3; ++d) {
+              const float gap = fmaxf(0.0f, fmaxf(lj[d] - hi[d], li[d] - hj[d]));
+              g2 += gap * gap * (d == 2 ? ib2 : ia2);
             }
-            const uint64_t mask = ballot(act);
-            if (act) plist[count + lanes_below(mask)] = pij;
+            act[r] = mypair[r] >= 0 && g2 < 1.0001f;
+            if (r % 2 == 1) __builtin_amdgcn_sched_barrier(0);   // box loads of two rounds in flight at most
+          }
+#pragma unroll
+          for (int r = 0; r < PR; ++r) {
+            const uint64_t mask = ballot(act[r]);
+            if (act[r]) plist[count + lanes_below(mask)] = mypair[r];
             count += __popcll(mask);
           }
           wave_sync();
@@ -581,7 +624,9 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             for (int rr = 0; rr < R; ++rr)
 #pragma unroll
               for (int d = 0; d < 3; ++d) {
-                const f4 cr = *reinterpret_cast<const f4*>(Ct + tile_at(d * NR + 16 * rr + col, 4 * grp));
+                f4* cp = reinterpret_cast<f4*>(Ct + tile_at(d * NR + 16 * rr + col, 4 * grp));
+                const f4 cr = *cp;
+                *cp = f4{0.0f, 0.0f, 0.0f, 0.0f};     // the accumulator is kept zero between tiles
 #pragma unroll
                 for (int s = 0; s < 4; ++s) gacc[rr][d] = mfma4(cr[s], b4[s], gacc[rr][d]);
               }
@@ -609,21 +654,6 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           }
         }
         __syncthreads();
-        // margins to the bounds after an evaluating iteration (every wave, identical values)
-        if (lane < n) {
-          if (eval_flags & 1) {
-            float mx = 0.0f;
-            for (int ww = 0; ww < W; ++ww) mx = fmaxf(mx, s_vmx[ww * NR + lane]);
-            mv = vmax - sqrtf(mx);
-            dv = 0.0f;
-          }
-          if (eval_flags & 2) {
-            float mx = 0.0f;
-            for (int ww = 0; ww < W; ++ww) mx = fmaxf(mx, s_amx[ww * NR + lane]);
-            ma = amax - sqrtf(mx);
-            da = 0.0f;
-          }
-        }
         // multiplier step (all coefficients) and QP step (free coefficients) of row (robot, axis),
         // owned by thread 16R * axis + robot:
         // g = F^T rho R summed over the waves, lambda <- lambda - g,
@@ -636,72 +666,110 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           for (int ww = 0; ww < W; ++ww) g += gp0[ww * L.per_wave + q];
           return g;
         };
-        // pinned coefficients: multiplier step only (and their boundary values in the first step),
-        // on the waves that do not run the QP step when there are any
-        if (W == TAILW || wave >= TAILW) {
-          constexpr int base = W > TAILW ? 64 * TAILW : 0;
-          for (int q = tid - base; q < n * 3 * kNFix; q += nthr - base) {
-            const int row = q / kNFix, r = q - row * kNFix;
-            const int qq = row * m + fixed_k(r);
-            slam[qq] = slam[qq] - gsum(qq);
-            if (k == 0) sxi[qq] = pinned(row, r);
-          }
-        }
-        if (wave < TAILW) {
-          float y[MFX];
+        // Loads below use clamped (always valid) addresses and only the stores are guarded, so
+        // that all loads of a step issue back to back.
+        if (wave < TAILW && mf > 0) {
+          const int row = t_on ? t_row : 0;
+          float y[MFY], ln[MFX], xv[MFX];
 #pragma unroll
-          for (int f = 0; f < MFX; ++f) y[f] = 0.0f;
-          if (t_on) {
-            float gv[MFX], lv[MFX], bv_[MFX], xv[MFX], cv[MFX];
+          for (int f = 0; f < MFY; ++f) y[f] = 0.0f;
+          // in chunks of 4 coefficients: the loads of a chunk issue together
 #pragma unroll
-            for (int f = 0; f < MFX; ++f) {
-              gv[f] = lv[f] = bv_[f] = xv[f] = cv[f] = 0.0f;
-              if (f < mf) {
-                const int q = t_row * m + 3 + f;
-                gv[f] = gsum(q);
-                lv[f] = slam[q];
-                bv_[f] = sxb[q];
+          for (int c0 = 0; c0 < MFX; c0 += 4) {
+            float gv[4], lv[4], bq[4], cv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int f = c0 + j;
+              if (f < MFX) {
+                const int fc = min(f, mf - 1);
+                const int q = row * m + 3 + fc;
+                gv[j] = gsum(q);
+                lv[j] = slam[q];
+                bq[j] = sxb[q];
                 xv[f] = sxi[q];
-                if (k == 0) cv[f] = scorr[t_row * mf + f];
+                cv[j] = scorr[row * mf + fc];
               }
             }
 #pragma unroll
-            for (int f = 0; f < MFX; ++f) {
-              if (f < mf) {
-                const float ln = lv[f] - gv[f];
-                slam[t_row * m + 3 + f] = ln;
-                float yv = bv_[f] - xv[f] + ln - gv[f];
-                if (k == 0) yv += cv[f];
-                y[f] = yv;
+            for (int j = 0; j < 4; ++j) {
+              const int f = c0 + j;
+              if (f < MFX) {
+                ln[f] = lv[j] - gv[j];
+                float yv = bq[j] - xv[f] + ln[f] - gv[j];
+                if (k == 0) yv += cv[j];
+                y[f] = (t_on && f < mf) ? yv : 0.0f;
               }
             }
           }
-          float yb[MFX];
+          float yb[MFY];
 #pragma unroll
-          for (int f = 0; f < MFX; ++f) yb[f] = f < mf ? group_sum<NR>(y[f]) * inv_n : 0.0f;
+          for (int f = 0; f < MFY; ++f) yb[f] = f < MFX ? group_sum<NR>(y[f]) * inv_n : 0.0f;
+          // xi_free += X1 y + X01 mean(y), accumulated over f2 in order
+          float acc[MFY];
+#pragma unroll
+          for (int f = 0; f < MFY; ++f) acc[f] = 0.0f;
+#pragma unroll
+          for (int f2 = 0; f2 < MFX; ++f2) {
+            f4 a[MFY / 4], bm[MFY / 4];
+            const int rc = min(f2, mf - 1);
+#pragma unroll
+            for (int cc = 0; cc < MFY / 4; ++cc) {
+              a[cc] = *reinterpret_cast<const f4*>(sX1 + rc * kQPRow + 4 * cc);
+              bm[cc] = *reinterpret_cast<const f4*>(sX01 + rc * kQPRow + 4 * cc);
+            }
+            if (f2 < mf) {
+#pragma unroll
+              for (int f = 0; f < MFY; ++f) {
+                acc[f] = fmaf(a[f / 4][f % 4], y[f2], acc[f]);
+                acc[f] = fmaf(bm[f / 4][f % 4], yb[f2], acc[f]);
+              }
+            }
+          }
           if (t_on) {
             float dmax = 0.0f;
 #pragma unroll
             for (int f = 0; f < MFX; ++f) {
               if (f < mf) {
-                float acc = 0.0f;
-#pragma unroll
-                for (int cc = 0; cc < MFX / 4; ++cc) {
-                  if (4 * cc < mf) {
-                    const f4 a = *reinterpret_cast<const f4*>(sX1 + f * kQPRow + 4 * cc);
-                    const f4 b = *reinterpret_cast<const f4*>(sX01 + f * kQPRow + 4 * cc);
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                      acc = fmaf(a[j], y[4 * cc + j], acc);
-                      acc = fmaf(b[j], yb[4 * cc + j], acc);
-                    }
-                  }
-                }
-                sxi[t_row * m + 3 + f] += acc;
-                dmax = fmaxf(dmax, fabsf(acc));
+                const float xn = xv[f] + acc[f];
+                slam[row * m + 3 + f] = ln[f];
+                sxi[row * m + 3 + f] = xn;
+                if constexpr (MP != 0) put_split(t_rb, t_ax, 3 + f, xn);
+                dmax = fmaxf(dmax, fabsf(acc[f]));
               }
             }
-            s_dxi[t_row] = dmax;
+            s_dxi[row] = dmax;
+          }
+        } else if (wave < TAILW && t_on) {
+          s_dxi[t_row] = 0.0f;
+        }
+        // pinned coefficients: multiplier step only (and their boundary values in the first step),
+        // on the waves that do not run the QP step when there are any
+        if (W == TAILW || wave >= TAILW) {
+          constexpr int base = W > TAILW ? 64 * TAILW : 0;
+          constexpr int FT = 64 * W - base;
+          constexpr int J = (3 * NR * kNFix + FT - 1) / FT;
+          const int nfix = n * 3 * kNFix;
+          int qq[J];
+          float nl[J];
+#pragma unroll
+          for (int j = 0; j < J; ++j) {
+            const int qc = min(tid - base + j * FT, nfix - 1);
+            const int rw = qc / kNFix, r = qc - rw * kNFix;
+            qq[j] = rw * m + fixed_k(r);
+            nl[j] = slam[qq[j]] - gsum(qq[j]);
+          }
+#pragma unroll
+          for (int j = 0; j < J; ++j) {
+            const int q = tid - base + j * FT;
+            if (q < nfix) {
+              slam[qq[j]] = nl[j];
+              if (k == 0) {
+                const int rw = q / kNFix, r = q - rw * kNFix;
+                const float xp = pinned(rw, r);
+                sxi[qq[j]] = xp;
+                if constexpr (MP != 0) put_split(rw / 3, rw - (rw / 3) * 3, fixed_k(r), xp);
+              }
+            }
           }
         }
         __syncthreads();
@@ -803,7 +871,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                   const float px = Yn[rr][0][r] - (vx - f * vx);
                   const float py = Yn[rr][1][r] - (vy - f * vy);
                   const float pz = Yn[rr][2][r] - (vz - f * vz);
-                  const float nrm = px * px + py * py + pz * pz;
+                  const float nrm = 4 * grp + r < nt ? px * px + py * py + pz * pz : 0.0f;   // grid times only
                   ss += nrm;
                   mx = fmaxf(mx, nrm);
                 }
@@ -893,7 +961,7 @@ __global__ void reset_queue_kernel(int* queue) {
 // Kernel instances: R robot tiles of 16, KS k-steps of 4 coefficients, W waves per workgroup.
 constexpr int kW = 4;
 // Target waves per SIMD: the register budget that fits each instance without spills.
-constexpr int waves_per_simd(int R, int MP) { return (R == 1 && MP == 0) ? 3 : (R == 1 ? 2 : (MP == 0 ? 2 : 1)); }
+constexpr int waves_per_simd(int R, int MP) { return R == 1 ? (MP == 0 ? 3 : 2) : 1; }
 
 FastArgs make_fast_args(const LaunchArgs& a, const float* tab32, const uint4* a16) {
   FastArgs f;
@@ -910,9 +978,9 @@ template <int R, int KS, int W, int MP>
 hipError_t launch_instance(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16) {
   auto kern = fast_project_kernel<R, KS, W, MP, waves_per_simd(R, MP)>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes_w[W / 2 - 1]);
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes[W / 2 - 1][MP]);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(a.n_items), dim3(64 * W), p.lds_bytes_w[W / 2 - 1], a.stream, make_fast_args(a, tab32, a16));
+  hipLaunchKernelGGL(kern, dim3(a.n_items), dim3(64 * W), p.lds_bytes[W / 2 - 1][MP], a.stream, make_fast_args(a, tab32, a16));
   return hipGetLastError();
 }
 
@@ -960,11 +1028,13 @@ void a32_fill(const DevCfg& c, const double* P3, float* out) {
     for (int b = 0; b < 3; ++b)
       for (int lane = 0; lane < 64; ++lane) {
         const int col = lane & 15, grp = lane >> 4;
-        float* a = out + ((((size_t)tau * 3 + b) * 2 + 0) * 64 + lane) * 4;   // S1: P[t = 16 tau + col][k = 4 s + grp]
+        // S1: P[t = 16 tau + col][k = 4 s + grp], times past the horizon repeat the last grid time (so
+        // every row of the product is a real point of the trajectory); S4: zero past the horizon
+        float* a = out + ((((size_t)tau * 3 + b) * 2 + 0) * 64 + lane) * 4;
         float* bq = out + ((((size_t)tau * 3 + b) * 2 + 1) * 64 + lane) * 4;  // S4: rho P[t = 16 tau + 4 grp + s][k = col]
         for (int s = 0; s < 4; ++s) {
-          const int t = 16 * tau + col, k = 4 * s + grp;
-          a[s] = (t < c.H && k < c.m) ? (float)P3[((size_t)b * c.H + t) * c.m + k] : 0.0f;
+          const int t = std::min(16 * tau + col, c.H - 1), k = 4 * s + grp;
+          a[s] = k < c.m ? (float)P3[((size_t)b * c.H + t) * c.m + k] : 0.0f;
           const int t4 = 16 * tau + 4 * grp + s;
           bq[s] = (t4 < c.H && col < c.m) ? (float)(rho[b] * P3[((size_t)b * c.H + t4) * c.m + col]) : 0.0f;
         }
@@ -978,11 +1048,11 @@ void a16_fill(const DevCfg& c, const double* P3, int precision, uint16_t* out) {
     for (int b = 0; b < 3; ++b)
       for (int inst = 0; inst < 2; ++inst)
         for (int lane = 0; lane < 64; ++lane) {
-          const int col = lane & 15, grp = lane >> 4, t = 16 * tau + col;
+          const int col = lane & 15, grp = lane >> 4, t = std::min(16 * tau + col, c.H - 1);
           for (int v = 0; v < 8; ++v) {
             const int k = 8 * (grp & 1) + v;
             uint16_t bits = 0;
-            if (t < c.H && k < c.m) {
+            if (k < c.m) {
               const double P = P3[((size_t)b * c.H + t) * c.m + k];
               const uint16_t hi = bf ? bf16_bits((float)P) : f16_bits((float)P);
               const double hv = bf ? bf16_value(hi) : f16_value(hi);
@@ -1023,9 +1093,11 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
     maxKS = std::max(maxKS, (c.m + 3) / 4);
     maxNT = std::max(maxNT, (c.H + 15) / 16);
     for (int wi = 0; wi < 2; ++wi)
-      out.lds_bytes_w[wi] = std::max(out.lds_bytes_w[wi], (size_t)fast_lds_plan(c, c.n <= 16 ? 1 : 2, 2 * (wi + 1)).total * 4);
+      for (int mp = 0; mp < 3; ++mp)
+        out.lds_bytes[wi][mp] = std::max(out.lds_bytes[wi][mp],
+                                         (size_t)fast_lds_plan(c, c.n <= 16 ? 1 : 2, 2 * (wi + 1), mp).total * 4);
   }
-  if (out.lds_bytes_w[1] > 160 * 1024) return SF_OK;
+  if (out.lds_bytes[1][1] > 160 * 1024) return SF_OK;
   const DevCfg& c0 = cfgs[probs[0].cfg];
   out.KS = maxKS;
   out.R = c0.n <= 16 ? 1 : 2;
@@ -1039,7 +1111,7 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
     // resident work items at W waves per workgroup for the register budget of each precision
     auto slots = [&](int W, int mp) {
       const int by_waves = (4 * waves_per_simd(out.batched ? 2 : out.R, mp)) / W;
-      const int by_lds = (int)((160 * 1024) / std::max<size_t>(out.lds_bytes_w[W / 2 - 1], 1));
+      const int by_lds = (int)((160 * 1024) / std::max<size_t>(out.lds_bytes[W / 2 - 1][mp], 1));
       return (int64_t)std::max(1, std::min(by_waves, by_lds)) * out.ncu;
     };
     const int64_t ni = (int64_t)items.size();
@@ -1069,7 +1141,7 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
       return SF_ENOMEM;
     }
     const int wdef = out.Wp[SF_FP32 & 3];
-    const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(out.lds_bytes_w[wdef / 2 - 1], 1))));
+    const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(out.lds_bytes[wdef / 2 - 1][0], 1))));
     out.grid = std::min<int>((int)items.size(), out.ncu * per_cu);
   }
   out.ok = true;
@@ -1090,12 +1162,12 @@ template <int KS, int W, int MP>
 hipError_t launch_batched(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16, int grid) {
   auto kern = fast_batched_kernel<KS, W, MP, waves_per_simd(2, MP)>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes_w[W / 2 - 1]);
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes[W / 2 - 1][MP]);
   if (e != hipSuccess) return e;
   FastArgs f = make_fast_args(a, tab32, a16);
   f.items = p.d_items_sorted;
   hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, a.stream, p.d_queue);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * W), p.lds_bytes_w[W / 2 - 1], a.stream, f, p.d_queue);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * W), p.lds_bytes[W / 2 - 1][MP], a.stream, f, p.d_queue);
   return hipGetLastError();
 }
 
