@@ -5,6 +5,10 @@ residual), inputs resident in HBM.  The headline form (BF16-MFMA basis products 
 correction terms by default) is timed for exactly --steps calls; the plain FP32 solver is timed
 beside it on the same inputs, and both are judged at the same final feasibility tolerance.
 Prints one JSON line.
+
+Other workloads (not the headline): --workload swarm32 (32 robots, 4096 samples), ragged (3000
+problems of 8/16/32 robots in one persistent, graph-captured, autotuned launch) and diff16
+(forward with checkpoints + adjoint, gradient evaluations per second).
 """
 import argparse
 import hashlib
@@ -21,21 +25,30 @@ FEAS_TOL = 1e-3          # m, m/s, m/s^2 at the grid times, checked in FP64
 PEAKS = {                # published MI355X peaks
     "fp32_vector_tflops": 157.3,
     "fp64_vector_tflops": 78.6,
+    "fp32_mfma_tflops": 157.3,
+    "bf16_mfma_tflops": 2500.0,
+    "fp16_mfma_tflops": 2500.0,
 }
 DTYPES = {"fp64": "f64", "fp32": "f32", "bf16": "f32 state, bf16 MFMA basis products",
           "fp16": "f32 state, f16 MFMA basis products"}
 
 
-def flops_per_sample_iter(cfg):
-    """Algorithmic flops of one iteration for one sample (multiply-add = 2), counted as
-    basis evaluation 6nDHm, back-projection to the free coefficients 6nDHm_f, the Gram
-    product 4nDm m_f, pair projections 15 N_p H, bound balls 24nH, the pair scatter
-    2 N_p H D, the multiplier/target update 5nDm_f and the QP product 2D(n m_f)^2."""
+def flops_split(cfg):
+    """Algorithmic flops of one iteration for one sample (multiply-add = 2), split into the dense
+    contractions (basis evaluation 6nDHm, back-projection to the free coefficients 6nDHm_f, the
+    Gram product 4nDm m_f, the QP product 2D(n m_f)^2) and the elementwise VALU work (pair
+    projections 15 N_p H, bound balls 24nH, pair scatter 2 N_p H D, multiplier/target update
+    5nDm_f).  Returns (contractions, elementwise)."""
     n, D, m, H = cfg.n_robots, cfg.dims, cfg.degree + 1, cfg.horizon
     mf = m - 6
     Np = n * (n - 1) // 2
-    return (6 * n * D * H * m + 6 * n * D * H * mf + 4 * n * D * m * mf + 15 * Np * H + 24 * n * H
-            + 2 * Np * H * D + 5 * n * D * mf + 2 * D * (n * mf) ** 2)
+    dense = 6 * n * D * H * m + 6 * n * D * H * mf + 4 * n * D * m * mf + 2 * D * (n * mf) ** 2
+    elem = 15 * Np * H + 24 * n * H + 2 * Np * H * D + 5 * n * D * mf
+    return dense, elem
+
+
+def flops_per_sample_iter(cfg):
+    return sum(flops_split(cfg))
 
 
 def kernel_source_digest():
@@ -64,35 +77,26 @@ def measured_traffic(workload, precision):
     return int(kib * 1024)
 
 
-def cpu_baseline(workload, n_samples, iters):
+def cpu_baseline(problem, n_samples, iters):
     """The FP64 oracle on a bounded sample of the same workload, on the host cores."""
     import torch
     import oracle as O
-    p = workload.problems[0]
-    s = O.build_system(p.cfg)
-    xb = torch.tensor(p.xi_bar[:n_samples])
-    bv = torch.tensor(p.bvals)
+    s = O.build_system(problem.cfg)
+    xb = torch.tensor(problem.xi_bar[:n_samples])
+    bv = torch.tensor(problem.bvals)
     t0 = time.perf_counter()
     O.sf_project(s, xb, bv, iters)
     dt = time.perf_counter() - t0
     return {"value": round(n_samples / dt, 2), "unit": "projections/s", "cores": torch.get_num_threads(),
             "kind": "oracle",
-            "sample": f"first {n_samples} of {p.xi_bar.shape[0]} samples, {iters} iterations, "
+            "sample": f"first {n_samples} of {problem.xi_bar.shape[0]} samples, {iters} iterations, "
                       f"FP64 torch CPU ({dt:.1f} s)"}
 
 
-def run_form(sf, xb, bv, K, prec, steps, warmup, generic, graph, autotune=True):
-    """Time `steps` calls of one form; returns (ms per call, outputs).  The autotuner (launch
-    shape chosen by timing on this batch) runs inside the first warm-up call."""
+def time_calls(call, steps, warmup):
+    """Run `warmup` untimed calls (at least one: the autotuner, when asked for, runs inside the
+    first), then time exactly `steps` calls with events on the current stream."""
     import torch
-    S = xb.shape[0]
-    bufs = None
-    if graph:
-        from paper_2501_19042_amd import ProjectResult
-        bufs = ProjectResult(torch.empty_like(xb), torch.empty_like(xb),
-                             torch.empty((S, 2), dtype=xb.dtype, device=xb.device), None)
-    call = lambda: sf.project(xb, bv, K, precision=prec, generic=generic, graph=graph, out=bufs,
-                              autotune=autotune and not generic)
     out = None
     for _ in range(max(1, warmup)):
         out = call()
@@ -108,11 +112,144 @@ def run_form(sf, xb, bv, K, prec, steps, warmup, generic, graph, autotune=True):
     return ev0.elapsed_time(ev1) / steps, out
 
 
-def judge(sf, out, bv, prec):
-    viol = sf.feasibility(out.xi, bv, precision=prec).cpu()
+def judge(sf, out_xi, bv, prec, batch=None):
+    viol = sf.feasibility(out_xi, bv, batch=batch, precision=prec).cpu()
     worst = viol[:, :3].amax(1).clamp_min(viol[:, 3])
     feas = worst <= FEAS_TOL
     return int(feas.sum()), float(worst.quantile(0.99)), float(worst.max())
+
+
+def roofline(cfg_counts, iters, ms, prec, traffic):
+    """Contract roofline (all algorithmic flops against the FP32 vector peak) plus the split
+    bound: contractions against the MFMA peak of their dtype, elementwise work against the
+    vector peak, the larger of the two times as the floor."""
+    dense = sum(flops_split(c)[0] * k for c, k in cfg_counts) * iters
+    elem = sum(flops_split(c)[1] * k for c, k in cfg_counts) * iters
+    t = ms / 1e3
+    peak = PEAKS["fp64_vector_tflops"] if prec == "fp64" else PEAKS["fp32_vector_tflops"]
+    achieved = (dense + elem) / t / 1e12
+    mfma_peak = PEAKS.get(f"{prec}_mfma_tflops", PEAKS["fp32_mfma_tflops"])
+    floor = max(dense / (mfma_peak * 1e12), elem / (peak * 1e12))
+    n_units = sum(k for _, k in cfg_counts)
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": traffic,
+            "flops_per_sample_iter": round((dense + elem) / iters / n_units, 1), "kernel_ms": round(ms, 4),
+            "split": {"contraction_flops": dense, "elementwise_flops": elem, "mfma_peak": mfma_peak,
+                      "floor_ms": round(floor * 1e3, 4), "frac": round(floor / t, 4)},
+            "note": "dense algorithmic flops of the method; the MFMA kernel skips exact zeros"}
+
+
+def base_line(args, metric, value, ms, dtype, config, scaling="weak"):
+    return {"metric": metric, "value": round(value, 1), "unit": "projections/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+            "scaling": scaling, "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic (seeded straight-line Bernstein fits + Gaussian coefficient noise)", "config": config}
+
+
+def run_single(args, wl):
+    """One problem with many samples (16- or 32-robot swarm): headline form + comparison form."""
+    import torch
+    from paper_2501_19042_amd import SafetyFilter
+    p = wl.problems[0]
+    prec = args.precision
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    sf = SafetyFilter([p.cfg])
+    xb = torch.tensor(p.xi_bar, dtype=dt, device="cuda")
+    bv = torch.tensor(p.bvals, dtype=dt, device="cuda")
+    S, K = xb.shape[0], wl.iters
+
+    def form(pr, steps, warmup):
+        bufs = None
+        if args.graph:
+            from paper_2501_19042_amd import ProjectResult
+            bufs = ProjectResult(torch.empty_like(xb), torch.empty_like(xb),
+                                 torch.empty((S, 2), dtype=xb.dtype, device=xb.device), None)
+        call = lambda: sf.project(xb, bv, K, precision=pr, generic=args.generic, graph=args.graph, out=bufs,
+                                  autotune=not args.generic)
+        return time_calls(call, steps, warmup)
+
+    ms, out = form(prec, args.steps, args.warmup)
+    n_conv, p99, vmax = judge(sf, out.xi, bv, prec)
+    traffic = None if (args.generic or prec == "fp64") else measured_traffic(args.workload, prec)
+    line = base_line(args, f"converged SF projections/sec ({p.cfg.n_robots} robots, 3D); BF16-MFMA vs FP32 at equal residual",
+                     n_conv / (ms / 1e3), ms, DTYPES[prec],
+                     {"workload": wl.name, "samples": S, "robots": p.cfg.n_robots, "dims": p.cfg.dims,
+                      "degree": p.cfg.degree, "horizon": p.cfg.horizon, "iters": K, "precision": prec,
+                      "kernel": "generic" if args.generic else "mfma", "graph": args.graph})
+    line.update({"converged_fraction": round(n_conv / S, 6), "violation_p99": p99, "violation_max": vmax,
+                 "all_samples_per_s": round(S / (ms / 1e3), 1),
+                 "roofline": roofline([(p.cfg, S)], K, ms, prec, traffic)})
+    if args.compare != "none" and args.compare != prec and prec != "fp64":
+        ms2, out2 = form(args.compare, max(3, args.steps // 2), 1)
+        n2, p99b, vmaxb = judge(sf, out2.xi, bv, args.compare)
+        dev = ((out.xi - out2.xi).abs().reshape(S, -1).amax(1) / out2.xi.abs().reshape(S, -1).amax(1)).cpu()
+        line["compare"] = {
+            "precision": args.compare, "ms_per_step": round(ms2, 4), "value": round(n2 / (ms2 / 1e3), 1),
+            "converged_fraction": round(n2 / S, 6), "violation_p99": p99b, "violation_max": vmaxb,
+            "speedup_of_headline": round(ms2 / ms, 3),
+            "per_sample_rel_deviation_max": float(dev.max()), "per_sample_rel_deviation_median": float(dev.median()),
+        }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(p, min(args.cpu_samples, S), K)
+    return line
+
+
+def run_ragged(args, wl):
+    """3000 problems of 8/16/32 robots, 1..256 samples each, in one persistent launch replayed
+    from a captured hipGraph, launch shape chosen by the autotuner."""
+    import numpy as np
+    import torch
+    from paper_2501_19042_amd import Batch, ProjectResult, SafetyFilter
+    prec = args.precision if args.precision != "fp64" else "fp32"
+    cfgs = sorted({p.cfg for p in wl.problems}, key=lambda c: c.n_robots)
+    slot = {c: i for i, c in enumerate(cfgs)}
+    sf = SafetyFilter(cfgs)
+    batch = Batch([(slot[p.cfg], p.xi_bar.shape[0]) for p in wl.problems])
+    xb = torch.tensor(np.concatenate([p.xi_bar.ravel() for p in wl.problems]), dtype=torch.float32, device="cuda")
+    bv = torch.tensor(np.concatenate([p.bvals.ravel() for p in wl.problems]), dtype=torch.float32, device="cuda")
+    S, K = batch.n_samples, wl.iters
+    bufs = ProjectResult(torch.empty_like(xb), torch.empty_like(xb),
+                         torch.empty((S, 2), dtype=torch.float32, device="cuda"), None)
+    call = lambda: sf.project(xb, bv, K, batch=batch, precision=prec, graph=True, autotune=True, out=bufs)
+    ms, out = time_calls(call, args.steps, args.warmup)
+    n_conv, p99, vmax = judge(sf, out.xi, bv, prec, batch=batch)
+    counts = {}
+    for p in wl.problems:
+        counts[p.cfg] = counts.get(p.cfg, 0) + p.xi_bar.shape[0]
+    line = base_line(args, "converged SF projections/sec (ragged batch: 3000 problems of 8/16/32 robots, 3D)",
+                     n_conv / (ms / 1e3), ms, DTYPES[prec],
+                     {"workload": wl.name, "problems": len(wl.problems), "samples": S,
+                      "samples_by_robots": {str(c.n_robots): k for c, k in counts.items()}, "iters": K,
+                      "precision": prec, "kernel": "mfma persistent", "graph": True, "autotune": True})
+    line.update({"converged_fraction": round(n_conv / S, 6), "violation_p99": p99, "violation_max": vmax,
+                 "all_samples_per_s": round(S / (ms / 1e3), 1),
+                 "roofline": roofline(list(counts.items()), K, ms, prec, None)})
+    return line
+
+
+def run_diff(args, wl):
+    """Differentiation form: forward with checkpoints every 10 iterations + hand-written adjoint,
+    gradient of a loss on the projected trajectories with respect to the initialisation."""
+    import torch
+    from paper_2501_19042_amd import SafetyFilter
+    p = wl.problems[0]
+    sf = SafetyFilter([p.cfg])
+    xb = torch.tensor(p.xi_bar, dtype=torch.float32, device="cuda")
+    bv = torch.tensor(p.bvals, dtype=torch.float32, device="cuda")
+    S, K, ce = xb.shape[0], wl.iters, wl.ckpt_every
+    g_xi = torch.randn_like(xb)
+    g_res = torch.ones((S,), dtype=torch.float32, device="cuda")
+
+    def call():
+        out = sf.project(xb, bv, K, xi0=xb, lam0=torch.zeros_like(xb), ckpt_every=ce, generic=True)
+        return sf.project_backward(xb, bv, K, out.ckpt, ce, g_xi_out=g_xi, g_resid=g_res)
+    ms, _ = time_calls(call, args.steps, args.warmup)
+    line = base_line(args, "SF gradient evaluations/sec (16 robots, 3D, 100 unrolled iterations, checkpoints every 10)",
+                     S / (ms / 1e3), ms, "f32",
+                     {"workload": wl.name, "samples": S, "robots": p.cfg.n_robots, "iters": K, "ckpt_every": ce,
+                      "kernels": "generic forward with checkpoints + adjoint"})
+    line["unit"] = "gradients/s"
+    return line
 
 
 def main():
@@ -120,7 +257,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="swarm16", choices=["swarm16", "swarm32", "tiny2d"])
+    ap.add_argument("--workload", default="swarm16", choices=["swarm16", "swarm32", "tiny2d", "ragged", "diff16"])
     ap.add_argument("--precision", default="bf16", choices=["fp64", "fp32", "bf16", "fp16"])
     ap.add_argument("--compare", default="fp32", choices=["fp32", "bf16", "fp16", "none"],
                     help="second form timed beside the headline one")
@@ -146,64 +283,14 @@ def main():
         return
 
     import workloads as W
-    from paper_2501_19042_amd import SafetyFilter
-
     torch.cuda.set_device(0)
     wl = W.WORKLOADS[args.workload]()
-    p = wl.problems[0]
-    prec = args.precision
-    dt = torch.float64 if prec == "fp64" else torch.float32
-    sf = SafetyFilter([p.cfg])
-    xb = torch.tensor(p.xi_bar, dtype=dt, device="cuda")
-    bv = torch.tensor(p.bvals, dtype=dt, device="cuda")
-    S = xb.shape[0]
-    K = wl.iters
-
-    ms, out = run_form(sf, xb, bv, K, prec, args.steps, args.warmup, args.generic, args.graph)
-    n_conv, p99, vmax = judge(sf, out, bv, prec)
-    value = n_conv / (ms / 1e3)
-
-    W_it = flops_per_sample_iter(p.cfg)
-    achieved = W_it * S * K / (ms / 1e3) / 1e12
-    peak = PEAKS["fp64_vector_tflops"] if prec == "fp64" else PEAKS["fp32_vector_tflops"]
-    traffic = None if (args.generic or prec == "fp64") else measured_traffic(args.workload, prec)
-    line = {
-        "metric": "converged SF projections/sec (16 robots, 3D); BF16-MFMA vs FP32 at equal residual",
-        "value": round(value, 1),
-        "unit": "projections/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": DTYPES[prec],
-        "data": "synthetic (seeded straight-line Bernstein fits + Gaussian coefficient noise)",
-        "config": {"workload": wl.name, "samples": S, "robots": p.cfg.n_robots, "dims": p.cfg.dims,
-                   "degree": p.cfg.degree, "horizon": p.cfg.horizon, "iters": K, "precision": prec,
-                   "kernel": "generic" if args.generic else "mfma", "graph": args.graph},
-        "converged_fraction": round(n_conv / S, 6),
-        "violation_p99": p99,
-        "violation_max": vmax,
-        "all_samples_per_s": round(S / (ms / 1e3), 1),
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": traffic,
-                     "flops_per_sample_iter": W_it, "kernel_ms": round(ms, 4),
-                     "note": "dense algorithmic flops of the method; the MFMA kernel skips exact zeros"},
-    }
-    if args.compare != "none" and args.compare != prec and prec != "fp64":
-        ms2, out2 = run_form(sf, xb, bv, K, args.compare, max(3, args.steps // 2), 1, args.generic, False)
-        n2, p99b, vmaxb = judge(sf, out2, bv, args.compare)
-        dev = ((out.xi - out2.xi).abs().reshape(S, -1).amax(1) / out2.xi.abs().reshape(S, -1).amax(1)).cpu()
-        line["compare"] = {
-            "precision": args.compare, "ms_per_step": round(ms2, 4), "value": round(n2 / (ms2 / 1e3), 1),
-            "converged_fraction": round(n2 / S, 6), "violation_p99": p99b, "violation_max": vmaxb,
-            "speedup_of_headline": round(ms2 / ms, 3),
-            "per_sample_rel_deviation_max": float(dev.max()), "per_sample_rel_deviation_median": float(dev.median()),
-        }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_samples, S), K)
+    if args.workload == "ragged":
+        line = run_ragged(args, wl)
+    elif args.workload == "diff16":
+        line = run_diff(args, wl)
+    else:
+        line = run_single(args, wl)
     print(json.dumps(line), flush=True)
 
 
