@@ -270,7 +270,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus above 1 is not supported "
-                                   "(samples shard across GPUs without communication, see the design notes)"}))
+                                   "(samples are independent: a multi-GPU run would give each GPU a cost-balanced slice of the problem table)"}))
         sys.exit(2)
     import torch
     if args.copy_calibration:

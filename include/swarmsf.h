@@ -49,8 +49,11 @@ typedef enum {
 typedef enum {
   SF_FP64 = 0,          /* everything in double precision */
   SF_FP32 = 1,          /* everything in single precision */
-  SF_BF16 = 2,          /* fixed-matrix products in bf16 MFMA + fp32 correction */
-  SF_FP16 = 3           /* fixed-matrix products in fp16 MFMA + fp32 correction */
+  SF_BF16 = 2,          /* basis products in bf16 MFMA with the rounding residuals of both factors
+                           fed back as fp32-accumulated correction terms; fp32 state */
+  SF_FP16 = 3           /* the same with fp16.  SF_BF16 / SF_FP16 need a batch the MFMA kernels
+                           cover (3D, n_robots <= 32, degree <= 15, horizon <= 256) and no
+                           SF_RESID_HISTORY, else SF_EUNSUPPORTED */
 } sf_precision;
 
 /* Flags for sf_project. */
@@ -58,13 +61,16 @@ typedef enum {
 #define SF_GENERIC_KERNEL 2  /* use the generic LDS kernel even where the MFMA kernel applies */
 #define SF_USE_GRAPH 4       /* capture the launch sequence in a hipGraph on first use (per plan and
                                 argument set) and replay it; the first call must not be under capture */
-#define SF_AUTOTUNE 8        /* time the persistent launch's candidate grid sizes on this batch (on the
-                                first call; synchronizes) and keep the fastest, also in the JSON-lines
-                                cache $SWARMSF_TUNE_CACHE (default ~/.cache/swarmsf_tune.jsonl) */
+#define SF_AUTOTUNE 8        /* on the first call for a batch and precision (synchronizes): time the
+                                MFMA launch candidates (2 or 4 waves per sample; for persistent launches
+                                also 1-6 workgroups per CU) on 20 iterations of this batch and keep the
+                                fastest, also in the JSON-lines cache $SWARMSF_TUNE_CACHE (default
+                                ~/.cache/swarmsf_tune.jsonl) for later processes */
 #define SF_PERSISTENT 16     /* run a single-shape batch through the persistent work-queue kernel (a
                                 batch of mixed swarm sizes always uses it on the MFMA path) */
 
-/* One problem shape (eqs. poly, inter_robot_con; bounds per the design notes).
+/* One problem shape (eqs. poly, inter_robot_con; the velocity and acceleration bounds are
+ * origin-centred balls in the polar form of eq. workspace_polar with d in [0, 1]).
  *  n_robots >= 2, dims in {2, 3}, degree >= 5 (Bernstein), horizon >= degree + 1,
  *  grid tau_h = h / (horizon - 1), h = 0..horizon-1, over [0, t_final] seconds.
  *  safety_a, safety_b: semi-axes of the centre-to-centre spheroid M_a = diag(a, a, b)

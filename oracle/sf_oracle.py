@@ -8,7 +8,7 @@ xi-step solves the full KKT system of eq. (xi_step) with a library LU
 factorisation.  Everything is float64 PyTorch on the CPU, so autograd through
 this module gives reference gradients.
 
-Readings of the paper taken here (each is listed in the design notes):
+Readings of the paper taken here, where it is silent, ambiguous or garbled:
   * lambda step: lambda <- lambda - rho F^T (F xi - e).  The printed "+" in
     eq. (lambda_step) contradicts the -<lambda, xi> term of eq. (aug_lag) and the
     +lambda of eta; with "+" the iteration diverges.

@@ -628,7 +628,7 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
   }
   if (precision > SF_FP32 && !fp)
     return fail(SF_EUNSUPPORTED, "the MFMA precisions need a batch the MFMA kernels cover "
-                                 "(3D, up to 32 robots, degree <= 15, horizon <= 128) and no residual history");
+                                 "(3D, up to 32 robots, degree <= 15, horizon <= 256) and no residual history");
   if (!fp) {
     st = pick_tile(h, p, elem, generic_bytes, &a.tile, &a.lds_bytes);
     if (st != SF_OK) return st;
