@@ -18,6 +18,11 @@ namespace {
 
 thread_local std::string g_err;
 
+// Margin of the MFMA kernel's reusable pair lists, as a fraction of the safety semi-axes: a
+// list built with it stays a superset of the colliding pairs until some robot has moved that
+// far along an axis (then it is rebuilt).
+constexpr double kPairSkin = 0.1;
+
 sf_status fail(sf_status s, const std::string& msg) {
   g_err = msg;
   return s;
@@ -174,6 +179,7 @@ sf_status build_cfg(const sf_config& c, HostCfg& out) {
   // round the bounds up so that the fp32 copies used on the device stay upper bounds
   d.lip_v *= 1.0 + 1e-6;
   d.lip_a *= 1.0 + 1e-6;
+  d.skin = kPairSkin;
   std::vector<double>& t = out.tab;
   t.clear();
   d.off_basis = t.size();

@@ -86,10 +86,14 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
 // LDS plan (in 4-byte words).  Per-wave tile buffers: positions Xt and collision residual
 // accumulator Ct as [axis][robot (16R)][time] with 16-word rows whose four 16-byte chunks are
 // XOR-swizzled by the robot index (tile_at), so that the 16-byte accesses of 16 consecutive lanes
-// hit distinct banks; boxes bb [robot][8]; list of the pairs that survive the broad phase.  Once
+// hit distinct banks; boxes bb [robot][kBoxRow]; per tile, the list of pairs that can collide.  Once
 // its time tiles are done, a wave reuses its own region for its partial back-projection (nDm
 // words) and, after the final residual pass, for its partial sums.
 constexpr int kQPRow = 12;               // padded row of the QP matrices in LDS (m_f <= 10)
+// Row strides (words) chosen so that the 16-byte accesses of 16 consecutive robots hit 16
+// distinct groups of 4 banks (64 banks): boxes (lo xyz _, hi xyz _, pad) and 16-bit operands.
+constexpr int kBoxRow = 12;
+constexpr int kHBRow = 20;
 struct FastLds {
   int xi, lam, xb, xprev, dbar, corr, pairs, vmx, amx, dxi, qp, hb, tiles, per_wave, total;
   int xt, ct, bb, plist;   // offsets inside one wave's tile region
@@ -113,13 +117,14 @@ __host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W, 
   o = (o + 3) & ~3;
   p.qp = o; o += 2 * c.mf * kQPRow;        // X1, X01 with rows padded to kQPRow floats
   o = (o + 3) & ~3;
-  p.hb = o; o += MP ? 3 * nr * 16 : 0;     // 16-bit S1 B operands: [axis][robot][hi x16, lo x16]
+  p.hb = o; o += MP ? 3 * nr * kHBRow : 0; // 16-bit S1 B operands: [axis][robot][hi x16, lo x16, pad]
   o = (o + 3) & ~3;                        // 16-byte alignment of the tile buffers
   p.xt = 0;
   p.ct = 3 * nr * 16;
   p.bb = 6 * nr * 16;
-  p.plist = p.bb + 8 * nr;
-  int pw = p.plist + Npmax;
+  p.plist = p.bb + kBoxRow * nr;           // per tile of the wave: [count, pairs...] kept across iterations
+  const int NT = (c.H + 15) / 16, TQ = (NT + W - 1) / W;
+  int pw = p.plist + TQ * (Npmax + 1);
   if (pw < nDm) pw = nDm;
   if (pw < 128) pw = 128;
   p.per_wave = (pw + 3) & ~3;
@@ -270,14 +275,13 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
     auto put_split = [&](int robot, int d, int kk, float x) {
       const HE hi = static_cast<HE>(x);
       const HE lo = static_cast<HE>(x - static_cast<float>(hi));
-      shb[(d * NR + robot) * 32 + kk] = hi;
-      shb[(d * NR + robot) * 32 + 16 + kk] = lo;
+      shb[(d * NR + robot) * (2 * kHBRow) + kk] = hi;
+      shb[(d * NR + robot) * (2 * kHBRow) + 16 + kk] = lo;
     };
     float* wbuf = smem + L.tiles + wave * L.per_wave;
     float* Xt = wbuf + L.xt;
     float* Ct = wbuf + L.ct;
     float* bb = wbuf + L.bb;
-    int* plist = reinterpret_cast<int*>(wbuf + L.plist);
     // pinned coefficient r of a robot-axis row after the first step: Bmap (p0, v0, a0, pH, vH, aH)
     auto pinned = [&](int row, int r) {
       float acc = 0.0f;
@@ -352,6 +356,11 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
       // the last evaluation and accumulated bound on the drift since then
       float mv = -1.0f, dv = 0.0f, ma = -1.0f, da = 0.0f;
       int prev_eval = 0;
+      // pair lists: accumulated bound on the position change of robot `lane` per axis since the lists
+      // were built (a position is a convex combination of its coefficients, so it moves by at most
+      // the largest change of a coefficient)
+      float px_ = 0.0f, py_ = 0.0f, pz_ = 0.0f;
+      const float skx = (float)(c.skin * c.a) * 0.999f, skz = (float)(c.skin * c.b) * 0.999f;
 
       for (int k = 0; k < iters; ++k) {
         // Lane-dependent indices are re-derived from an opaque copy every iteration: otherwise the
@@ -400,6 +409,9 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             }
             const float d0 = s_dxi[lane * 3], d1 = s_dxi[lane * 3 + 1], d2 = s_dxi[lane * 3 + 2];
             dn = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+            px_ += d0;
+            py_ += d1;
+            pz_ += d2;
           }
           dv += Lv * dn;
           da += La * dn;
@@ -408,6 +420,10 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           if (k >= 2) eval_flags = (ballot(fv) != 0 ? 1 : 0) | (ballot(fa) != 0 ? 2 : 0);
         }
         prev_eval = eval_flags;
+        // Rebuild the pair lists when some robot may have moved by more than the margin they were
+        // built with (and in iterations 0 and 1, where the pinned coefficients jump).
+        const bool rebuild = k < 2 || ballot(lane < n && (px_ > skx || py_ > skx || pz_ > skz)) != 0;
+        if (rebuild) px_ = py_ = pz_ = 0.0f;
         // S1 B operand: xi^T, lane (col, grp) holds robot col, coefficient 4 s + grp
         float bx[MP == 0 ? R : 1][3][KS];
         typename Half<MP == 0 ? 1 : MP>::V hb1[MP == 0 ? 1 : R][3], hb2[MP == 0 ? 1 : R][3];
@@ -429,7 +445,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           for (int rr = 0; rr < R; ++rr)
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-              const uint4* hrow = reinterpret_cast<const uint4*>(shb + (d * NR + 16 * rr + col) * 32);
+              const uint4* hrow = reinterpret_cast<const uint4*>(shb + (d * NR + 16 * rr + col) * (2 * kHBRow));
               hb1[rr][d] = __builtin_bit_cast(V, hrow[grp & 1]);
               const uint4 lo = hrow[2 + (grp & 1)];
               hb2[rr][d] = __builtin_bit_cast(V, grp < 2 ? lo : uint4{0u, 0u, 0u, 0u});
@@ -514,7 +530,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
               }
             // (rows past the horizon repeat the last grid time, so all 16 rows count)
 #pragma unroll
-            for (int rr = 0; rr < R; ++rr) {
+            for (int rr = 0; rr < R && rebuild; ++rr) {
               float lo[3], hi[3];
 #pragma unroll
               for (int d = 0; d < 3; ++d) {
@@ -523,7 +539,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                 hi[d] = grp_max(fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
               }
               if (grp == 0) {
-                float* bq = bb + (16 * rr + col) * 8;
+                float* bq = bb + (16 * rr + col) * kBoxRow;
                 *reinterpret_cast<f4*>(bq) = f4{lo[0], lo[1], lo[2], 0.0f};
                 *reinterpret_cast<f4*>(bq + 4) = f4{hi[0], hi[1], hi[2], 0.0f};
               }
@@ -567,22 +583,30 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             }
           }
           wave_sync();
-          // ---- S2: broad phase over the tile, narrow phase on the surviving pairs ----
+          // ---- S2: broad phase over the tile (when the lists are rebuilt), narrow phase on the list ----
+          // A pair is listed when its boxes, shrunk by twice the margin per axis, are closer than the
+          // safety distance (scaled, 1e-4 relative slack); until the next rebuild no unlisted pair can
+          // come closer than the safety distance, so its residual is exactly zero.
           // (unused lanes test the pair (0, 1) and discard the result, so all box loads issue at once)
+          int* tl = reinterpret_cast<int*>(wbuf + L.plist) + q * (NR * (NR - 1) / 2 + 1);
           int count = 0;
+          if (rebuild) {
           bool act[PR];
 #pragma unroll
           for (int r = 0; r < PR; ++r) {
             const int pij = mypair[r] >= 0 ? mypair[r] : (1 << 8);
             const int i = pij & 255, j = pij >> 8;
-            const f4 li = *reinterpret_cast<const f4*>(bb + i * 8);
-            const f4 hi = *reinterpret_cast<const f4*>(bb + i * 8 + 4);
-            const f4 lj = *reinterpret_cast<const f4*>(bb + j * 8);
-            const f4 hj = *reinterpret_cast<const f4*>(bb + j * 8 + 4);
+            const f4 li = *reinterpret_cast<const f4*>(bb + i * kBoxRow);
+            const f4 hi = *reinterpret_cast<const f4*>(bb + i * kBoxRow + 4);
+            const f4 lj = *reinterpret_cast<const f4*>(bb + j * kBoxRow);
+            const f4 hj = *reinterpret_cast<const f4*>(bb + j * kBoxRow + 4);
             float g2 = 0.0f;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-              const float gap = fmaxf(0.0f, fmaxf(lj[d] - hi[d], li[d] - hj[d]));
+              // the list is reused on later iterations' positions, whose rounding differs from these
+              // by a few 1e-5 of the coordinates at most (16-bit split products): 2^-12 covers it
+              const float tol = 2.44140625e-4f * fmaxf(fmaxf(fabsf(li[d]), fabsf(hi[d])), fmaxf(fabsf(lj[d]), fabsf(hj[d])));
+              const float gap = fmaxf(0.0f, fmaxf(lj[d] - hi[d], li[d] - hj[d]) - 2.0f * (d == 2 ? skz : skx) - tol);
               g2 += gap * gap * (d == 2 ? ib2 : ia2);
             }
             act[r] = mypair[r] >= 0 && g2 < 1.0001f;
@@ -591,15 +615,19 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
 #pragma unroll
           for (int r = 0; r < PR; ++r) {
             const uint64_t mask = ballot(act[r]);
-            if (act[r]) plist[count + lanes_below(mask)] = mypair[r];
+            if (act[r]) tl[1 + count + lanes_below(mask)] = mypair[r];
             count += __popcll(mask);
           }
+          if (lane == 0) tl[0] = count;
           wave_sync();
+          } else {
+            count = __builtin_amdgcn_readfirstlane(tl[0]);
+          }
           bool nzc = false;
           for (int base = 0; base < count; base += 4) {
             const int slot = base + grp;
             if (slot < count && col < nt) {
-              const int pij = plist[slot];
+              const int pij = tl[1 + slot];
               const int i = pij & 255, j = pij >> 8;
               const float rx = Xt[tile_at(0 * NR + i, col)] - Xt[tile_at(0 * NR + j, col)];
               const float ry = Xt[tile_at(1 * NR + i, col)] - Xt[tile_at(1 * NR + j, col)];

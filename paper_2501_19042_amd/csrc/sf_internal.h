@@ -24,6 +24,8 @@ struct DevCfg {
   double a, b, inv_a2, inv_b2, vmax, amax;
   double rho_c, rho_v, rho_a, n_rho_c;
   double lip_v, lip_a;    // max_t sum_k |Pd[t][k]|, max_t sum_k |Pdd[t][k]|: drift bounds of v, acc
+  double skin;            // pair-list margin of the MFMA broad phase, as a fraction of the safety
+                          // semi-axes (a for x, y; b for z)
   int64_t off_basis, off_X1, off_X01, off_Bmap, off_Gfx, off_Rfx;
   int64_t off_a16[2];     // 16-byte offsets of the bf16 / fp16 S1 operand tables (MFMA path)
   int64_t off_a32;        // 16-byte offset of the fp32 S1 operand table (MFMA path)
