@@ -9,6 +9,15 @@
 
 namespace sf {
 
+// Work items of one robot-tile class (R tiles of 16 robots) in a persistent launch sequence.
+struct FastClass {
+  int R = 0;
+  int offset = 0;                       // first item in FastPlan::d_items_sorted
+  int n_items = 0;
+  int grid = 0;                         // default persistent workgroups
+  size_t lds_bytes[2][3] = {};          // LDS per workgroup for W = 2, 4 and fp32 / bf16 / fp16
+};
+
 struct FastPlan {
   bool ok = false;              // the batch is covered by the fast kernels
   int R = 0;                    // robot tiles of 16 (single-shape batches)
@@ -18,10 +27,11 @@ struct FastPlan {
   size_t lds_bytes[2][3] = {};          // LDS per workgroup for W = 2, 4 and fp32 / bf16 / fp16
   // persistent launch over a ragged batch (mixed swarm sizes, or requested)
   bool batched = false;
-  WorkItem* d_items_sorted = nullptr;   // work items, most expensive first
-  int* d_queue = nullptr;               // work-queue head, reset by a kernel before each launch
+  WorkItem* d_items_sorted = nullptr;   // work items by class, most expensive first within a class
+  int* d_queue = nullptr;               // work-queue heads (one per class), reset by a kernel before each launch
+  FastClass cls[2];                     // 17-32 robots, then up to 16 (empty classes left out)
+  int n_cls = 0;
   int ncu = 0;
-  int grid = 0;                         // default persistent workgroups
   int tuned_grid[4] = {0, 0, 0, 0};     // autotuned persistent workgroups per precision (0 = not tuned)
   int tuned_w[4] = {0, 0, 0, 0};        // autotuned waves per workgroup per precision (0 = not tuned)
 };

@@ -962,10 +962,10 @@ fast_project_kernel(FastArgs A) {
   for (int it = blockIdx.x; it < A.n_items; it += gridDim.x) fast_item<R, KS, W, MP>(A, it, smem);
 }
 
-// Persistent kernel over a ragged batch: workgroups pull work items (sorted by decreasing cost
-// on the host) from an atomic queue until it is empty; each item runs the body for its swarm
-// size (up to 16 robots, or up to 32).  Every wave reaches the exit once the queue is drained.
-template <int KS, int W, int MP, int WPE>
+// Persistent kernel over the work items of one robot-tile class (R tiles of 16 robots) of a
+// ragged batch: workgroups pull items (sorted by decreasing cost on the host) from an atomic
+// queue until it is empty.  Every wave reaches the exit once the queue is drained.
+template <int R, int KS, int W, int MP, int WPE>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 fast_batched_kernel(FastArgs A, int* __restrict__ queue) {
   extern __shared__ __align__(16) float smem[];
@@ -976,14 +976,15 @@ fast_batched_kernel(FastArgs A, int* __restrict__ queue) {
     const int it = __builtin_amdgcn_readfirstlane(next);
     __syncthreads();
     if (it >= A.n_items) break;
-    const int n = A.cfgs[A.probs[A.items[it].problem].cfg].n;
-    if (n <= 16) fast_item<1, KS, W, MP>(A, it, smem);
-    else fast_item<2, KS, W, MP>(A, it, smem);
+    fast_item<R, KS, W, MP>(A, it, smem);
   }
 }
 
-__global__ void reset_queue_kernel(int* queue) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *queue = 0;
+// Resets the queue heads of a launch sequence (a kernel node rather than a memset, so the
+// sequence can be captured in a graph).
+__global__ void reset_queue_kernel(int* queue, int n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    for (int i = 0; i < n; ++i) queue[i] = 0;
 }
 
 // Kernel instances: R robot tiles of 16, KS k-steps of 4 coefficients, W waves per workgroup.
@@ -1138,7 +1139,7 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
     out.ncu = ncu > 0 ? ncu : 256;
     // resident work items at W waves per workgroup for the register budget of each precision
     auto slots = [&](int W, int mp) {
-      const int by_waves = (4 * waves_per_simd(out.batched ? 2 : out.R, mp)) / W;
+      const int by_waves = (4 * waves_per_simd(mixed ? 2 : out.R, mp)) / W;
       const int by_lds = (int)((160 * 1024) / std::max<size_t>(out.lds_bytes[W / 2 - 1][mp], 1));
       return (int64_t)std::max(1, std::min(by_waves, by_lds)) * out.ncu;
     };
@@ -1149,28 +1150,42 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
     }
   }
   if (out.batched) {
-    // longest-processing-time order: most expensive work items first
-    std::vector<std::pair<double, int>> order(items.size());
+    // One persistent launch per robot-tile class (17-32 robots first, then up to 16), each kernel
+    // compiled for its own register budget; inside a class, longest-processing-time order.
+    std::vector<std::pair<double, int>> order[2];
     for (size_t i = 0; i < items.size(); ++i) {
-      const DevProblem& p = probs[items[i].problem];
-      order[i] = {item_cost(cfgs[p.cfg], items[i].count), (int)i};
+      const DevCfg& c = cfgs[probs[items[i].problem].cfg];
+      order[c.n > 16 ? 0 : 1].push_back({item_cost(c, items[i].count), (int)i});
     }
-    std::stable_sort(order.begin(), order.end(),
-                     [](const std::pair<double, int>& a, const std::pair<double, int>& b) { return a.first > b.first; });
-    std::vector<WorkItem> sorted(items.size());
-    for (size_t i = 0; i < items.size(); ++i) sorted[i] = items[order[i].second];
+    std::vector<WorkItem> sorted;
+    const int wdef = out.Wp[SF_FP32 & 3];
+    for (int k = 0; k < 2; ++k) {
+      if (order[k].empty()) continue;
+      std::stable_sort(order[k].begin(), order[k].end(),
+                       [](const std::pair<double, int>& a, const std::pair<double, int>& b) { return a.first > b.first; });
+      FastClass& C = out.cls[out.n_cls++];
+      C.R = k == 0 ? 2 : 1;
+      C.offset = (int)sorted.size();
+      C.n_items = (int)order[k].size();
+      for (const auto& o : order[k]) {
+        sorted.push_back(items[o.second]);
+        const DevCfg& c = cfgs[probs[items[o.second].problem].cfg];
+        for (int wi = 0; wi < 2; ++wi)
+          for (int mp = 0; mp < 3; ++mp)
+            C.lds_bytes[wi][mp] = std::max(C.lds_bytes[wi][mp], (size_t)fast_lds_plan(c, C.R, 2 * (wi + 1), mp).total * 4);
+      }
+      const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(C.lds_bytes[wdef / 2 - 1][0], 1))));
+      C.grid = std::min(C.n_items, out.ncu * per_cu);
+    }
     hipError_t e = hipMalloc(&out.d_items_sorted, sorted.size() * sizeof(WorkItem));
     if (e == hipSuccess)
       e = hipMemcpy(out.d_items_sorted, sorted.data(), sorted.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc(&out.d_queue, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&out.d_queue, 2 * sizeof(int));
     if (e != hipSuccess) {
       fast_plan_free(out);
       g_fast_err = "persistent plan allocation failed";
       return SF_ENOMEM;
     }
-    const int wdef = out.Wp[SF_FP32 & 3];
-    const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(out.lds_bytes[wdef / 2 - 1][0], 1))));
-    out.grid = std::min<int>((int)items.size(), out.ncu * per_cu);
   }
   out.ok = true;
   return SF_OK;
@@ -1186,17 +1201,32 @@ void fast_plan_free(FastPlan& p) {
 
 namespace {
 
+template <int R, int KS, int W, int MP>
+hipError_t launch_class(const FastClass& C, const FastArgs& f, int grid, int* queue, hipStream_t stream) {
+  auto kern = fast_batched_kernel<R, KS, W, MP, waves_per_simd(R, MP)>;
+  const size_t lds = C.lds_bytes[W / 2 - 1][MP];
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * W), lds, stream, f, queue);
+  return hipGetLastError();
+}
+
+// grid > 0: workgroups per class launch (at most its work items); 0: each class's default.
 template <int KS, int W, int MP>
 hipError_t launch_batched(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16, int grid) {
-  auto kern = fast_batched_kernel<KS, W, MP, waves_per_simd(2, MP)>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes[W / 2 - 1][MP]);
-  if (e != hipSuccess) return e;
-  FastArgs f = make_fast_args(a, tab32, a16);
-  f.items = p.d_items_sorted;
-  hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, a.stream, p.d_queue);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * W), p.lds_bytes[W / 2 - 1][MP], a.stream, f, p.d_queue);
-  return hipGetLastError();
+  hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, a.stream, p.d_queue, p.n_cls);
+  for (int ci = 0; ci < p.n_cls; ++ci) {
+    const FastClass& C = p.cls[ci];
+    FastArgs f = make_fast_args(a, tab32, a16);
+    f.items = p.d_items_sorted + C.offset;
+    f.n_items = C.n_items;
+    const int g = std::max(1, std::min(C.n_items, grid > 0 ? grid : C.grid));
+    const hipError_t e = C.R == 1 ? launch_class<1, KS, W, MP>(C, f, g, p.d_queue + ci, a.stream)
+                                  : launch_class<2, KS, W, MP>(C, f, g, p.d_queue + ci, a.stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <int MP>
@@ -1254,7 +1284,7 @@ hipError_t launch_mp(const FastPlan& p, const LaunchArgs& a, const float* tab32,
 hipError_t fast_launch(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16, int precision) {
   const int W = p.tuned_w[precision & 3] > 0 ? p.tuned_w[precision & 3] : p.Wp[precision & 3];
   if (p.batched) {
-    const int g = p.tuned_grid[precision & 3] > 0 ? p.tuned_grid[precision & 3] : p.grid;
+    const int g = p.tuned_grid[precision & 3];
     return fast_launch_batched(p, a, tab32, a16, precision, g, W);
   }
   return fast_launch_single(p, a, tab32, a16, precision, W);
