@@ -89,7 +89,7 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
 // hit distinct banks; boxes bb [robot][kBoxRow]; per tile, the list of pairs that can collide.  Once
 // its time tiles are done, a wave reuses its own region for its partial back-projection (nDm
 // words) and, after the final residual pass, for its partial sums.
-constexpr int kQPRow = 12;               // padded row of the QP matrices in LDS (m_f <= 10)
+constexpr int kQPCols = 16;              // QP matrix row in LDS: both halves, each padded (m_f <= 10)
 // Row strides (words) chosen so that the 16-byte accesses of 16 consecutive robots hit 16
 // distinct groups of 4 banks (64 banks): boxes (lo xyz _, hi xyz _, pad) and 16-bit operands.
 constexpr int kBoxRow = 12;
@@ -115,7 +115,7 @@ __host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W, 
   p.amx = o; o += W * nr;                  // same for the acceleration
   p.dxi = o; o += 3 * nr;                  // per (robot, axis): max |change| of a free coefficient
   o = (o + 3) & ~3;
-  p.qp = o; o += 2 * c.mf * kQPRow;        // X1, X01 with rows padded to kQPRow floats
+  p.qp = o; o += 2 * c.mf * kQPCols;       // X1, X01 transposed, rows of at most kQPCols floats
   o = (o + 3) & ~3;
   p.hb = o; o += MP ? 3 * nr * kHBRow : 0; // 16-bit S1 B operands: [axis][robot][hi x16, lo x16, pad]
   o = (o + 3) & ~3;                        // 16-byte alignment of the tile buffers
@@ -231,9 +231,11 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
   constexpr int NR = 16 * R;
   constexpr int PR = (NR * (NR - 1) / 2 + 63) / 64;   // 64-pair rounds of the broad phase
   constexpr int MFX = 4 * KS - 6;                     // free coefficients per robot-axis, at most
-  constexpr int MFY = (MFX + 3) & ~3;                 // ... padded to whole 16-byte chunks
-  static_assert(MFY <= kQPRow, "QP rows");
-  constexpr int TAILW = (3 * NR + 63) / 64;           // waves running the multiplier and QP steps
+  constexpr int HALVES = 6 * NR <= 64 * W ? 2 : 1;    // lanes per row in the multiplier/QP step
+  constexpr int FH = (MFX + HALVES - 1) / HALVES;     // free coefficients per lane
+  constexpr int FHP = (FH + 3) & ~3;                  // ... padded to whole 16-byte chunks
+  static_assert(HALVES * FHP <= kQPCols, "QP matrix rows");
+  constexpr int TAILW = (3 * NR * HALVES + 63) / 64;  // waves running the multiplier and QP steps
   static_assert(TAILW <= W, "the multiplier/QP step needs 3 x 16R lanes");
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -295,14 +297,14 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
       int p = i * n - i * (i + 1) / 2;
       for (int j = i + 1; j < n; ++j) spairs[p++] = i | (j << 8);
     }
-    // QP matrices X1 (relative motion) and X01 (mean motion minus relative), stored transposed
-    // (row f2 holds X[f][f2] for all f) with zero-padded rows
+    // QP matrices X1 (relative motion) and X01 (mean motion minus relative), transposed and cut
+    // into the halves of the outputs the lanes own: [matrix][half][f2][j] = X[half * FH + j][f2]
+    // (zero-padded)
     float* sX1 = smem + L.qp;
-    float* sX01 = sX1 + mf * kQPRow;
-    for (int q = tid; q < 2 * mf * kQPRow; q += nthr) {
-      const int mat = q / (mf * kQPRow), rem = q - mat * mf * kQPRow;
-      const int f2 = rem / kQPRow, f = rem - f2 * kQPRow;
-      sX1[q] = f < mf ? (mat == 0 ? X1 : X01)[f * mf + f2] : 0.0f;
+    for (int q = tid; q < 2 * HALVES * mf * FHP; q += nthr) {
+      const int j = q % FHP, f2 = (q / FHP) % mf, mh = q / (FHP * mf);
+      const int h = mh % HALVES, mat = mh / HALVES, f = h * FH + j;
+      sX1[q] = (j < FH && f < mf) ? (mat == 0 ? X1 : X01)[f * mf + f2] : 0.0f;
     }
     // basis operand tables: fp32 [tile][basis][S1 A operand, S4 B operand (x rho)][lane],
     // 16-bit [tile][basis][instruction][lane]
@@ -370,9 +372,6 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         asm volatile("" : "+v"(lane_o));
         const int tid = lane_o, lane = lane_o & 63;
         const int col = lane & 15, grp = lane >> 4;
-        const int t_ax = tid / NR, t_rb = tid - t_ax * NR;
-        const bool t_on = tid < 3 * NR && t_rb < n;
-        const int t_row = t_rb * 3 + t_ax;
         if (ckpt && (k % ckpt_every) == 0) {
           const int64_t base = (int64_t)(k / ckpt_every) * 2 * ckpt_stride + coef;
           for (int q = tid; q < nDm; q += nthr) {
@@ -623,25 +622,31 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           } else {
             count = __builtin_amdgcn_readfirstlane(tl[0]);
           }
+          // narrow phase: lanes cover (pair, time) items, 64 / T pairs per round with T = the tile's
+          // valid times rounded up to 4, 8 or 16; the next round's pair codes load meanwhile
+          const int tsh = nt <= 4 ? 2 : (nt <= 8 ? 3 : 4);
+          const int tt = lane & ((1 << tsh) - 1), ps = lane >> tsh, ppr = 64 >> tsh;
           bool nzc = false;
-          for (int base = 0; base < count; base += 4) {
-            const int slot = base + grp;
-            if (slot < count && col < nt) {
-              const int pij = tl[1 + slot];
+          int pnext = ps < count ? tl[1 + ps] : 0;
+          for (int base = 0; base < count; base += ppr) {
+            const int slot = base + ps;
+            const int pij = pnext;
+            pnext = slot + ppr < count ? tl[1 + slot + ppr] : 0;
+            if (slot < count && tt < nt) {
               const int i = pij & 255, j = pij >> 8;
-              const float rx = Xt[tile_at(0 * NR + i, col)] - Xt[tile_at(0 * NR + j, col)];
-              const float ry = Xt[tile_at(1 * NR + i, col)] - Xt[tile_at(1 * NR + j, col)];
-              const float rz = Xt[tile_at(2 * NR + i, col)] - Xt[tile_at(2 * NR + j, col)];
+              const float rx = Xt[tile_at(0 * NR + i, tt)] - Xt[tile_at(0 * NR + j, tt)];
+              const float ry = Xt[tile_at(1 * NR + i, tt)] - Xt[tile_at(1 * NR + j, tt)];
+              const float rz = Xt[tile_at(2 * NR + i, tt)] - Xt[tile_at(2 * NR + j, tt)];
               float Rx, Ry, Rz;
               coll_resid3(rx, ry, rz, ia2, ib2, sb, Rx, Ry, Rz);
               if (Rx != 0.0f || Ry != 0.0f || Rz != 0.0f) {
                 nzc = true;
-                atomicAdd(Ct + tile_at(0 * NR + i, col), Rx);
-                atomicAdd(Ct + tile_at(1 * NR + i, col), Ry);
-                atomicAdd(Ct + tile_at(2 * NR + i, col), Rz);
-                atomicAdd(Ct + tile_at(0 * NR + j, col), -Rx);
-                atomicAdd(Ct + tile_at(1 * NR + j, col), -Ry);
-                atomicAdd(Ct + tile_at(2 * NR + j, col), -Rz);
+                atomicAdd(Ct + tile_at(0 * NR + i, tt), Rx);
+                atomicAdd(Ct + tile_at(1 * NR + i, tt), Ry);
+                atomicAdd(Ct + tile_at(2 * NR + i, tt), Rz);
+                atomicAdd(Ct + tile_at(0 * NR + j, tt), -Rx);
+                atomicAdd(Ct + tile_at(1 * NR + j, tt), -Ry);
+                atomicAdd(Ct + tile_at(2 * NR + j, tt), -Rz);
               }
             }
           }
@@ -682,11 +687,15 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           }
         }
         __syncthreads();
-        // multiplier step (all coefficients) and QP step (free coefficients) of row (robot, axis),
-        // owned by thread 16R * axis + robot:
+        // Multiplier step (all coefficients) and QP step (free coefficients) of row (robot, axis):
         // g = F^T rho R summed over the waves, lambda <- lambda - g,
         // y = xi_bar - xi + lambda - g (+ the first-step correction), and
-        // xi_free += X1 y + X01 mean_robots(y)
+        // xi_free += X1 y + X01 mean_robots(y).
+        // With HALVES = 2 a row is owned by two lanes 32 apart in one wave, each taking half of its
+        // free and pinned coefficients; they swap their halves of y and mean(y) for the QP product.
+        // Rows are axis-major, so the robots of one axis sit in aligned groups of 16R lanes.
+        // Loads use clamped (always valid) addresses and only the stores are guarded, so that all
+        // loads of a step issue back to back.
         const float* gp0 = smem + L.tiles;
         auto gsum = [&](int q) {
           float g = 0.0f;
@@ -694,110 +703,108 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           for (int ww = 0; ww < W; ++ww) g += gp0[ww * L.per_wave + q];
           return g;
         };
-        // Loads below use clamped (always valid) addresses and only the stores are guarded, so
-        // that all loads of a step issue back to back.
-        if (wave < TAILW && mf > 0) {
-          const int row = t_on ? t_row : 0;
-          float y[MFY], ln[MFX], xv[MFX];
+        if (wave < TAILW) {
+          const int hl = HALVES == 2 ? (lane >> 5) : 0;
+          const int trow = wave * (64 / HALVES) + (HALVES == 2 ? (lane & 31) : lane);
+          const int ax = trow / NR, rb = trow - ax * NR;
+          const bool on = ax < 3 && rb < n;
+          const int row = on ? rb * 3 + ax : 0;
+          // pinned coefficients of the row: multiplier step, and their boundary values in step 0
+          constexpr int PF = kNFix / HALVES;
+          float nl[PF];
+          int qq[PF];
 #pragma unroll
-          for (int f = 0; f < MFY; ++f) y[f] = 0.0f;
-          // in chunks of 4 coefficients: the loads of a chunk issue together
-#pragma unroll
-          for (int c0 = 0; c0 < MFX; c0 += 4) {
-            float gv[4], lv[4], bq[4], cv[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int f = c0 + j;
-              if (f < MFX) {
-                const int fc = min(f, mf - 1);
-                const int q = row * m + 3 + fc;
-                gv[j] = gsum(q);
-                lv[j] = slam[q];
-                bq[j] = sxb[q];
-                xv[f] = sxi[q];
-                cv[j] = scorr[row * mf + fc];
-              }
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int f = c0 + j;
-              if (f < MFX) {
-                ln[f] = lv[j] - gv[j];
-                float yv = bq[j] - xv[f] + ln[f] - gv[j];
-                if (k == 0) yv += cv[j];
-                y[f] = (t_on && f < mf) ? yv : 0.0f;
-              }
-            }
-          }
-          float yb[MFY];
-#pragma unroll
-          for (int f = 0; f < MFY; ++f) yb[f] = f < MFX ? group_sum<NR>(y[f]) * inv_n : 0.0f;
-          // xi_free += X1 y + X01 mean(y), accumulated over f2 in order
-          float acc[MFY];
-#pragma unroll
-          for (int f = 0; f < MFY; ++f) acc[f] = 0.0f;
-#pragma unroll
-          for (int f2 = 0; f2 < MFX; ++f2) {
-            f4 a[MFY / 4], bm[MFY / 4];
-            const int rc = min(f2, mf - 1);
-#pragma unroll
-            for (int cc = 0; cc < MFY / 4; ++cc) {
-              a[cc] = *reinterpret_cast<const f4*>(sX1 + rc * kQPRow + 4 * cc);
-              bm[cc] = *reinterpret_cast<const f4*>(sX01 + rc * kQPRow + 4 * cc);
-            }
-            if (f2 < mf) {
-#pragma unroll
-              for (int f = 0; f < MFY; ++f) {
-                acc[f] = fmaf(a[f / 4][f % 4], y[f2], acc[f]);
-                acc[f] = fmaf(bm[f / 4][f % 4], yb[f2], acc[f]);
-              }
-            }
-          }
-          if (t_on) {
-            float dmax = 0.0f;
-#pragma unroll
-            for (int f = 0; f < MFX; ++f) {
-              if (f < mf) {
-                const float xn = xv[f] + acc[f];
-                slam[row * m + 3 + f] = ln[f];
-                sxi[row * m + 3 + f] = xn;
-                if constexpr (MP != 0) put_split(t_rb, t_ax, 3 + f, xn);
-                dmax = fmaxf(dmax, fabsf(acc[f]));
-              }
-            }
-            s_dxi[row] = dmax;
-          }
-        } else if (wave < TAILW && t_on) {
-          s_dxi[t_row] = 0.0f;
-        }
-        // pinned coefficients: multiplier step only (and their boundary values in the first step),
-        // on the waves that do not run the QP step when there are any
-        if (W == TAILW || wave >= TAILW) {
-          constexpr int base = W > TAILW ? 64 * TAILW : 0;
-          constexpr int FT = 64 * W - base;
-          constexpr int J = (3 * NR * kNFix + FT - 1) / FT;
-          const int nfix = n * 3 * kNFix;
-          int qq[J];
-          float nl[J];
-#pragma unroll
-          for (int j = 0; j < J; ++j) {
-            const int qc = min(tid - base + j * FT, nfix - 1);
-            const int rw = qc / kNFix, r = qc - rw * kNFix;
-            qq[j] = rw * m + fixed_k(r);
+          for (int j = 0; j < PF; ++j) {
+            qq[j] = row * m + fixed_k(hl * PF + j);
             nl[j] = slam[qq[j]] - gsum(qq[j]);
           }
+          // free coefficients f = hl * FH + j
+          float yo[FH], ln[FH], xv[FH];
 #pragma unroll
-          for (int j = 0; j < J; ++j) {
-            const int q = tid - base + j * FT;
-            if (q < nfix) {
-              slam[qq[j]] = nl[j];
-              if (k == 0) {
-                const int rw = q / kNFix, r = q - rw * kNFix;
-                const float xp = pinned(rw, r);
-                sxi[qq[j]] = xp;
-                if constexpr (MP != 0) put_split(rw / 3, rw - (rw / 3) * 3, fixed_k(r), xp);
+          for (int j = 0; j < FH; ++j) {
+            const int f = hl * FH + j;
+            const int fc = max(0, min(f, mf - 1));
+            const int q = row * m + 3 + fc;
+            const float g = gsum(q);
+            xv[j] = sxi[q];
+            ln[j] = slam[q] - g;
+            float yv = sxb[q] - xv[j] + ln[j] - g;
+            if (k == 0) yv += scorr[row * (mf > 0 ? mf : 1) + fc];
+            yo[j] = (on && f < mf) ? yv : 0.0f;
+          }
+          float ybo[FH];
+#pragma unroll
+          for (int j = 0; j < FH; ++j) ybo[j] = group_sum<NR>(yo[j]) * inv_n;
+          // all free coefficients' y and mean(y), in order
+          float ya[HALVES * FH], yba[HALVES * FH];
+#pragma unroll
+          for (int j = 0; j < FH; ++j) {
+            if constexpr (HALVES == 2) {
+              const auto sy = __builtin_amdgcn_permlane32_swap(__float_as_uint(yo[j]), __float_as_uint(yo[j]), false, false);
+              const auto sb2 = __builtin_amdgcn_permlane32_swap(__float_as_uint(ybo[j]), __float_as_uint(ybo[j]), false, false);
+              const float y0 = __uint_as_float(sy[0]), y1 = __uint_as_float(sy[1]);     // halves 0, 1
+              const float b0 = __uint_as_float(sb2[0]), b1 = __uint_as_float(sb2[1]);
+              ya[j] = y0;
+              ya[FH + j] = y1;
+              yba[j] = b0;
+              yba[FH + j] = b1;
+            } else {
+              ya[j] = yo[j];
+              yba[j] = ybo[j];
+            }
+          }
+          // own outputs: acc[j] = sum_f2 X1[f][f2] y[f2] + X01[f][f2] mean(y)[f2], f2 in order
+          float acc[FHP];
+#pragma unroll
+          for (int j = 0; j < FHP; ++j) acc[j] = 0.0f;
+#pragma unroll
+          for (int f2 = 0; f2 < HALVES * FH; ++f2) {
+            if (f2 < MFX) {
+              const int rc = max(0, min(f2, mf - 1));
+              f4 a1[FHP / 4], a2[FHP / 4];
+#pragma unroll
+              for (int cc = 0; cc < FHP / 4; ++cc) {
+                a1[cc] = *reinterpret_cast<const f4*>(sX1 + ((0 * HALVES + hl) * mf + rc) * FHP + 4 * cc);
+                a2[cc] = *reinterpret_cast<const f4*>(sX1 + ((1 * HALVES + hl) * mf + rc) * FHP + 4 * cc);
+              }
+              if (f2 < mf) {
+#pragma unroll
+                for (int j = 0; j < FHP; ++j) {
+                  acc[j] = fmaf(a1[j / 4][j % 4], ya[f2], acc[j]);
+                  acc[j] = fmaf(a2[j / 4][j % 4], yba[f2], acc[j]);
+                }
               }
             }
+          }
+          float dmax = 0.0f;
+#pragma unroll
+          for (int j = 0; j < FH; ++j)
+            if (hl * FH + j < mf) dmax = fmaxf(dmax, fabsf(acc[j]));
+          if constexpr (HALVES == 2) {
+            const auto sd = __builtin_amdgcn_permlane32_swap(__float_as_uint(dmax), __float_as_uint(dmax), false, false);
+            dmax = fmaxf(__uint_as_float(sd[0]), __uint_as_float(sd[1]));
+          }
+          if (on) {
+#pragma unroll
+            for (int j = 0; j < PF; ++j) {
+              slam[qq[j]] = nl[j];
+              if (k == 0) {
+                const float xp = pinned(row, hl * PF + j);
+                sxi[qq[j]] = xp;
+                if constexpr (MP != 0) put_split(rb, ax, fixed_k(hl * PF + j), xp);
+              }
+            }
+#pragma unroll
+            for (int j = 0; j < FH; ++j) {
+              const int f = hl * FH + j;
+              if (f < mf) {
+                const float xn = xv[j] + acc[j];
+                slam[row * m + 3 + f] = ln[j];
+                sxi[row * m + 3 + f] = xn;
+                if constexpr (MP != 0) put_split(rb, ax, 3 + f, xn);
+              }
+            }
+            if (hl == 0) s_dxi[row] = dmax;
           }
         }
         __syncthreads();
