@@ -180,7 +180,7 @@ def run_single(args, wl):
                  "all_samples_per_s": round(S / (ms / 1e3), 1),
                  "roofline": roofline([(p.cfg, S)], K, ms, prec, traffic)})
     if args.compare != "none" and args.compare != prec and prec != "fp64":
-        ms2, out2 = form(args.compare, max(3, args.steps // 2), 1)
+        ms2, out2 = form(args.compare, args.steps, args.warmup)
         n2, p99b, vmaxb = judge(sf, out2.xi, bv, args.compare)
         dev = ((out.xi - out2.xi).abs().reshape(S, -1).amax(1) / out2.xi.abs().reshape(S, -1).amax(1)).cpu()
         line["compare"] = {

@@ -62,7 +62,7 @@ typedef enum {
 #define SF_USE_GRAPH 4       /* capture the launch sequence in a hipGraph on first use (per plan and
                                 argument set) and replay it; the first call must not be under capture */
 #define SF_AUTOTUNE 8        /* on the first call for a batch and precision (synchronizes): time the
-                                MFMA launch candidates (2 or 4 waves per sample; for persistent launches
+                                MFMA launch candidates (2, 3 or 4 waves per sample; for persistent launches
                                 also 1-6 workgroups per CU) on 30 iterations of this batch (best of two runs) and keep the
                                 fastest, also in the JSON-lines cache $SWARMSF_TUNE_CACHE (default
                                 ~/.cache/swarmsf_tune.jsonl) for later processes */

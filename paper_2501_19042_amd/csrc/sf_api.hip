@@ -429,7 +429,7 @@ sf_status autotune(sf_handle h, const Plan* p, sf::FastPlan& fp, const sf::Launc
   }
   // candidates: waves per workgroup x (persistent only) workgroups in flight
   std::vector<std::pair<int, int>> cand;
-  for (int W : {2, 4}) {
+  for (int W : {2, 3, 4}) {
     if (!fp.batched) {
       cand.push_back({W, 0});
       continue;

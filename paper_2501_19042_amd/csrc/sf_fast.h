@@ -15,16 +15,16 @@ struct FastClass {
   int offset = 0;                       // first item in FastPlan::d_items_sorted
   int n_items = 0;
   int grid = 0;                         // default persistent workgroups
-  size_t lds_bytes[2][3] = {};          // LDS per workgroup for W = 2, 4 and fp32 / bf16 / fp16
+  size_t lds_bytes[3][3] = {};          // LDS per workgroup for W = 2, 3, 4 and fp32 / bf16 / fp16
 };
 
 struct FastPlan {
   bool ok = false;              // the batch is covered by the fast kernels
   int R = 0;                    // robot tiles of 16 (single-shape batches)
   int KS = 0;                   // k-steps of 4 coefficients (maximum over the batch)
-  int Wp[4] = {4, 4, 4, 4};     // default waves per workgroup (2 or 4) per precision; time tiles
+  int Wp[4] = {4, 4, 4, 4};     // default waves per workgroup (2, 3 or 4) per precision; time tiles
                                 // are dealt round-robin to the waves
-  size_t lds_bytes[2][3] = {};          // LDS per workgroup for W = 2, 4 and fp32 / bf16 / fp16
+  size_t lds_bytes[3][3] = {};          // LDS per workgroup for W = 2, 3, 4 and fp32 / bf16 / fp16
   // persistent launch over a ragged batch (mixed swarm sizes, or requested)
   bool batched = false;
   WorkItem* d_items_sorted = nullptr;   // work items by class, most expensive first within a class

@@ -997,7 +997,7 @@ __global__ void reset_queue_kernel(int* queue, int n) {
 // Kernel instances: R robot tiles of 16, KS k-steps of 4 coefficients, W waves per workgroup.
 constexpr int kW = 4;
 // Target waves per SIMD: the register budget that fits each instance without spills.
-constexpr int waves_per_simd(int R, int MP) { return R == 1 ? (MP == 0 ? 3 : 2) : 1; }
+constexpr int waves_per_simd(int R, int MP) { return R == 1 ? 3 : 1; }
 
 FastArgs make_fast_args(const LaunchArgs& a, const float* tab32, const uint4* a16) {
   FastArgs f;
@@ -1014,9 +1014,9 @@ template <int R, int KS, int W, int MP>
 hipError_t launch_instance(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16) {
   auto kern = fast_project_kernel<R, KS, W, MP, waves_per_simd(R, MP)>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes[W / 2 - 1][MP]);
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes[W - 2][MP]);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(a.n_items), dim3(64 * W), p.lds_bytes[W / 2 - 1][MP], a.stream, make_fast_args(a, tab32, a16));
+  hipLaunchKernelGGL(kern, dim3(a.n_items), dim3(64 * W), p.lds_bytes[W - 2][MP], a.stream, make_fast_args(a, tab32, a16));
   return hipGetLastError();
 }
 
@@ -1128,12 +1128,12 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
     if (p.cfg != probs[0].cfg) mixed = true;
     maxKS = std::max(maxKS, (c.m + 3) / 4);
     maxNT = std::max(maxNT, (c.H + 15) / 16);
-    for (int wi = 0; wi < 2; ++wi)
+    for (int wi = 0; wi < 3; ++wi)
       for (int mp = 0; mp < 3; ++mp)
         out.lds_bytes[wi][mp] = std::max(out.lds_bytes[wi][mp],
-                                         (size_t)fast_lds_plan(c, c.n <= 16 ? 1 : 2, 2 * (wi + 1), mp).total * 4);
+                                         (size_t)fast_lds_plan(c, c.n <= 16 ? 1 : 2, wi + 2, mp).total * 4);
   }
-  if (out.lds_bytes[1][1] > 160 * 1024) return SF_OK;
+  if (out.lds_bytes[2][1] > 160 * 1024) return SF_OK;
   const DevCfg& c0 = cfgs[probs[0].cfg];
   out.KS = maxKS;
   out.R = c0.n <= 16 ? 1 : 2;
@@ -1147,13 +1147,15 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
     // resident work items at W waves per workgroup for the register budget of each precision
     auto slots = [&](int W, int mp) {
       const int by_waves = (4 * waves_per_simd(mixed ? 2 : out.R, mp)) / W;
-      const int by_lds = (int)((160 * 1024) / std::max<size_t>(out.lds_bytes[W / 2 - 1][mp], 1));
+      const int by_lds = (int)((160 * 1024) / std::max<size_t>(out.lds_bytes[W - 2][mp], 1));
       return (int64_t)std::max(1, std::min(by_waves, by_lds)) * out.ncu;
     };
     const int64_t ni = (int64_t)items.size();
     for (int prec = SF_FP32; prec <= SF_FP16; ++prec) {
       const int mp = prec - SF_FP32;
-      out.Wp[prec & 3] = (ni > slots(4, mp) && ni <= slots(2, mp)) ? 2 : 4;
+      // the most waves per workgroup that still lets every work item be resident at once;
+      // with more items than that, 4 (throughput over latency)
+      out.Wp[prec & 3] = ni <= slots(4, mp) ? 4 : (ni <= slots(3, mp) ? 3 : (ni <= slots(2, mp) ? 2 : 4));
     }
   }
   if (out.batched) {
@@ -1177,11 +1179,11 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
       for (const auto& o : order[k]) {
         sorted.push_back(items[o.second]);
         const DevCfg& c = cfgs[probs[items[o.second].problem].cfg];
-        for (int wi = 0; wi < 2; ++wi)
+        for (int wi = 0; wi < 3; ++wi)
           for (int mp = 0; mp < 3; ++mp)
-            C.lds_bytes[wi][mp] = std::max(C.lds_bytes[wi][mp], (size_t)fast_lds_plan(c, C.R, 2 * (wi + 1), mp).total * 4);
+            C.lds_bytes[wi][mp] = std::max(C.lds_bytes[wi][mp], (size_t)fast_lds_plan(c, C.R, wi + 2, mp).total * 4);
       }
-      const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(C.lds_bytes[wdef / 2 - 1][0], 1))));
+      const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / std::max<size_t>(C.lds_bytes[wdef - 2][0], 1))));
       C.grid = std::min(C.n_items, out.ncu * per_cu);
     }
     hipError_t e = hipMalloc(&out.d_items_sorted, sorted.size() * sizeof(WorkItem));
@@ -1211,7 +1213,7 @@ namespace {
 template <int R, int KS, int W, int MP>
 hipError_t launch_class(const FastClass& C, const FastArgs& f, int grid, int* queue, hipStream_t stream) {
   auto kern = fast_batched_kernel<R, KS, W, MP, waves_per_simd(R, MP)>;
-  const size_t lds = C.lds_bytes[W / 2 - 1][MP];
+  const size_t lds = C.lds_bytes[W - 2][MP];
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -1242,10 +1244,13 @@ hipError_t launch_batched_mp(const FastPlan& p, const LaunchArgs& a, const float
   const int key = p.KS * 10 + W;
   switch (key) {
     case 22: return launch_batched<2, 2, MP>(p, a, tab32, a16, grid);
+    case 23: return launch_batched<2, 3, MP>(p, a, tab32, a16, grid);
     case 24: return launch_batched<2, 4, MP>(p, a, tab32, a16, grid);
     case 32: return launch_batched<3, 2, MP>(p, a, tab32, a16, grid);
+    case 33: return launch_batched<3, 3, MP>(p, a, tab32, a16, grid);
     case 34: return launch_batched<3, 4, MP>(p, a, tab32, a16, grid);
     case 42: return launch_batched<4, 2, MP>(p, a, tab32, a16, grid);
+    case 43: return launch_batched<4, 3, MP>(p, a, tab32, a16, grid);
     case 44: return launch_batched<4, 4, MP>(p, a, tab32, a16, grid);
     default:
       g_fast_err = "no persistent kernel instance for this shape";
@@ -1273,14 +1278,19 @@ hipError_t launch_mp(const FastPlan& p, const LaunchArgs& a, const float* tab32,
   const int key = p.R * 100 + p.KS * 10 + W;
   switch (key) {
     case 122: return launch_instance<1, 2, 2, MP>(p, a, tab32, a16);
+    case 123: return launch_instance<1, 2, 3, MP>(p, a, tab32, a16);
     case 124: return launch_instance<1, 2, 4, MP>(p, a, tab32, a16);
     case 132: return launch_instance<1, 3, 2, MP>(p, a, tab32, a16);
+    case 133: return launch_instance<1, 3, 3, MP>(p, a, tab32, a16);
     case 134: return launch_instance<1, 3, 4, MP>(p, a, tab32, a16);
     case 142: return launch_instance<1, 4, 2, MP>(p, a, tab32, a16);
+    case 143: return launch_instance<1, 4, 3, MP>(p, a, tab32, a16);
     case 144: return launch_instance<1, 4, 4, MP>(p, a, tab32, a16);
     case 232: return launch_instance<2, 3, 2, MP>(p, a, tab32, a16);
+    case 233: return launch_instance<2, 3, 3, MP>(p, a, tab32, a16);
     case 234: return launch_instance<2, 3, 4, MP>(p, a, tab32, a16);
     case 242: return launch_instance<2, 4, 2, MP>(p, a, tab32, a16);
+    case 243: return launch_instance<2, 4, 3, MP>(p, a, tab32, a16);
     case 244: return launch_instance<2, 4, 4, MP>(p, a, tab32, a16);
     default:
       g_fast_err = "no kernel instance for this shape";
