@@ -814,98 +814,94 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
       if (resid_out) {
         float ss = 0.0f, mx = 0.0f;
         if (iters > 0) {
-          float bp[MP == 0 ? R : 1][3][KS], bn[MP == 0 ? R : 1][3][KS];
-          typename Half<MP == 0 ? 1 : MP>::V pb1[MP == 0 ? 1 : R][3], pb2[MP == 0 ? 1 : R][3];
-          typename Half<MP == 0 ? 1 : MP>::V nb1[MP == 0 ? 1 : R][3], nb2[MP == 0 ? 1 : R][3];
-          if constexpr (MP == 0) {
+          // One basis product of a tile for the iterate in `src` (previous or new).  The B operands
+          // are formed per product (this runs once per solve), so that only one iterate's
+          // products are live at a time.
+          auto prod = [&](const float* src, int tau, int b, f4 (&Y)[R][3]) {
+            if constexpr (MP == 0) {
+              const float4 av = a32c[((tau * 3 + b) * 2) * 64 + lane];
+              const float a1[4] = {av.x, av.y, av.z, av.w};
 #pragma unroll
-            for (int rr = 0; rr < R; ++rr)
+              for (int rr = 0; rr < R; ++rr)
 #pragma unroll
-              for (int d = 0; d < 3; ++d)
+                for (int d = 0; d < 3; ++d) {
+                  f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                  const int robot = 16 * rr + col, kk = 4 * s + grp;
-                  const bool ok = robot < n && kk < m;
-                  bp[rr][d][s] = ok ? sxprev[(robot * 3 + d) * m + kk] : 0.0f;
-                  bn[rr][d][s] = ok ? sxi[(robot * 3 + d) * m + kk] : 0.0f;
+                  for (int s = 0; s < KS; ++s) {
+                    const int robot = 16 * rr + col, kk = 4 * s + grp;
+                    const float v = (robot < n && kk < m) ? src[(robot * 3 + d) * m + kk] : 0.0f;
+                    acc = mfma4(a1[s], v, acc);
+                  }
+                  Y[rr][d] = acc;
                 }
-          } else {
+            } else {
+              typedef typename Half<MP>::V V;
+              const uint4* at = a16c + ((tau * 3 + b) * 2) * 64 + lane;
+              const V A1 = __builtin_bit_cast(V, at[0]);
+              const V A2 = __builtin_bit_cast(V, at[64]);
 #pragma unroll
-            for (int rr = 0; rr < R; ++rr)
+              for (int rr = 0; rr < R; ++rr)
 #pragma unroll
-              for (int d = 0; d < 3; ++d) {
-                split_xi<MP>(sxprev, 16 * rr + col, n, m, d, grp, pb1[rr][d], pb2[rr][d]);
-                split_xi<MP>(sxi, 16 * rr + col, n, m, d, grp, nb1[rr][d], nb2[rr][d]);
-              }
-          }
+                for (int d = 0; d < 3; ++d) {
+                  V h1, h2;
+                  split_xi<MP>(src, 16 * rr + col, n, m, d, grp, h1, h2);
+                  f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                  acc = mfma16(A1, h1, acc);
+                  acc = mfma16(A2, h2, acc);
+                  Y[rr][d] = acc;
+                }
+            }
+          };
 #pragma unroll 1
           for (int q = 0; q < TQ; ++q) {
             const int tau = wave + W * q;
             if (tau >= NT) break;
             const int t0 = 16 * tau;
             const int nt = min(16, H - t0);
-#pragma unroll
+#pragma unroll 1
             for (int b = 0; b < 3; ++b) {
-              f4 Yp[R][3], Yn[R][3];
-              if constexpr (MP == 0) {
-                const float4 av = a32c[((tau * 3 + b) * 2) * 64 + lane];
-                const float a1[4] = {av.x, av.y, av.z, av.w};
-#pragma unroll
-                for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-                  for (int d = 0; d < 3; ++d) {
-                    f4 ap = {0.0f, 0.0f, 0.0f, 0.0f}, an = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                    for (int s = 0; s < KS; ++s) {
-                      ap = mfma4(a1[s], bp[rr][d][s], ap);
-                      an = mfma4(a1[s], bn[rr][d][s], an);
-                    }
-                    Yp[rr][d] = ap;
-                    Yn[rr][d] = an;
-                  }
-              } else {
-                typedef typename Half<MP>::V V;
-                const uint4* at = a16c + ((tau * 3 + b) * 2) * 64 + lane;
-                const V A1 = __builtin_bit_cast(V, at[0]);
-                const V A2 = __builtin_bit_cast(V, at[64]);
-#pragma unroll
-                for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-                  for (int d = 0; d < 3; ++d) {
-                    f4 ap = {0.0f, 0.0f, 0.0f, 0.0f}, an = {0.0f, 0.0f, 0.0f, 0.0f};
-                    ap = mfma16(A1, pb1[rr][d], ap);
-                    ap = mfma16(A2, pb2[rr][d], ap);
-                    an = mfma16(A1, nb1[rr][d], an);
-                    an = mfma16(A2, nb2[rr][d], an);
-                    Yp[rr][d] = ap;
-                    Yn[rr][d] = an;
-                  }
-              }
+              if (b > 0 && !(b == 1 ? c.vel_on : c.acc_on)) continue;
+              const float lim = b == 1 ? vmax : amax;
+              f4 Y[R][3];
+              prod(sxprev, tau, b, Y);
               if (b == 0) {
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr)
 #pragma unroll
-                  for (int d = 0; d < 3; ++d) {
-                    const int o = tile_at(d * NR + 16 * rr + col, 4 * grp);
-                    *reinterpret_cast<f4*>(Xt + o) = Yp[rr][d];
-                    *reinterpret_cast<f4*>(Ct + o) = Yn[rr][d];
+                  for (int d = 0; d < 3; ++d)
+                    *reinterpret_cast<f4*>(Xt + tile_at(d * NR + 16 * rr + col, 4 * grp)) = Y[rr][d];
+              } else {
+                // targets of the bound balls at the previous iterate: e = v - R(v)
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+                  for (int r = 0; r < 4; ++r) {
+                    const float vx = Y[rr][0][r], vy = Y[rr][1][r], vz = Y[rr][2][r];
+                    const float s2 = vx * vx + vy * vy + vz * vz;
+                    const float f = s2 > lim * lim ? 1.0f - lim * rsqrtf(s2) : 0.0f;
+                    Y[rr][0][r] = vx - f * vx;
+                    Y[rr][1][r] = vy - f * vy;
+                    Y[rr][2][r] = vz - f * vz;
                   }
+              }
+              f4 Yn[R][3];
+              prod(sxi, tau, b, Yn);
+              if (b == 0) {
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+                  for (int d = 0; d < 3; ++d)
+                    *reinterpret_cast<f4*>(Ct + tile_at(d * NR + 16 * rr + col, 4 * grp)) = Yn[rr][d];
                 continue;
               }
-              // bound balls: r_p = v_new - e(v_prev), e = v_prev - R(v_prev)
-              const bool on = b == 1 ? c.vel_on : c.acc_on;
-              if (!on) continue;
-              const float lim = b == 1 ? vmax : amax;
+              // bound balls: r_p = v_new - e(v_prev)
 #pragma unroll
               for (int rr = 0; rr < R; ++rr)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                  const float vx = Yp[rr][0][r], vy = Yp[rr][1][r], vz = Yp[rr][2][r];
-                  const float s2 = vx * vx + vy * vy + vz * vz;
-                  const float f = s2 > lim * lim ? 1.0f - lim * rsqrtf(s2) : 0.0f;
-                  const float px = Yn[rr][0][r] - (vx - f * vx);
-                  const float py = Yn[rr][1][r] - (vy - f * vy);
-                  const float pz = Yn[rr][2][r] - (vz - f * vz);
+                  const float px = Yn[rr][0][r] - Y[rr][0][r];
+                  const float py = Yn[rr][1][r] - Y[rr][1][r];
+                  const float pz = Yn[rr][2][r] - Y[rr][2][r];
                   const float nrm = 4 * grp + r < nt ? px * px + py * py + pz * pz : 0.0f;   // grid times only
                   ss += nrm;
                   mx = fmaxf(mx, nrm);
