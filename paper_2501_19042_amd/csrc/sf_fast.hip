@@ -237,11 +237,15 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
   static_assert(HALVES * FHP <= kQPCols, "QP matrix rows");
   constexpr int TAILW = (3 * NR * HALVES + 63) / 64;  // waves running the multiplier and QP steps
   static_assert(TAILW <= W, "the multiplier/QP step needs 3 x 16R lanes");
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int col = lane & 15, grp = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nthr = 64 * W;
   {
+    // per-lane indices from an opaque copy, so that the compiler keeps per-lane addresses next to
+    // their uses instead of hoisting them to the kernel entry and spilling them
+    int tid_i = threadIdx.x;
+    asm volatile("" : "+v"(tid_i));
+    const int tid = tid_i, lane = tid_i & 63;
+    const int col = lane & 15, grp = lane >> 4;
     const WorkItem w = items[it];
     const DevProblem pr = probs[w.problem];
     const DevCfg c = cfgs[pr.cfg];
@@ -316,6 +320,11 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
     for (int r = 0; r < PR; ++r) mypair[r] = (64 * r + lane < Np) ? spairs[64 * r + lane] : -1;
 
     for (int sl = w.first; sl < w.first + w.count; ++sl) {
+      // per-lane indices re-derived per sample from an opaque copy (see the iteration loop)
+      int tid_s = threadIdx.x;
+      asm volatile("" : "+v"(tid_s));
+      const int tid = tid_s, lane = tid_s & 63;
+      const int col = lane & 15, grp = lane >> 4;
       const int64_t coef = pr.coef_off + (int64_t)sl * nDm;
       const int64_t sidx = pr.sample_base + sl;
       for (int q = tid; q < nDm; q += nthr) {
