@@ -95,7 +95,8 @@ def cpu_baseline(problem, n_samples, iters):
 
 def time_calls(call, steps, warmup):
     """Run `warmup` untimed calls (at least one: the autotuner, when asked for, runs inside the
-    first), then time exactly `steps` calls with events on the current stream."""
+    first, and the first launches of a kernel grow its scratch backing), then time exactly `steps`
+    calls with events on the current stream."""
     import torch
     out = None
     for _ in range(max(1, warmup)):
@@ -165,7 +166,7 @@ def run_single(args, wl):
             bufs = ProjectResult(torch.empty_like(xb), torch.empty_like(xb),
                                  torch.empty((S, 2), dtype=xb.dtype, device=xb.device), None)
         call = lambda: sf.project(xb, bv, K, precision=pr, generic=args.generic, graph=args.graph, out=bufs,
-                                  autotune=not args.generic)
+                                  autotune=args.autotune and not args.generic)
         return time_calls(call, steps, warmup)
 
     ms, out = form(prec, args.steps, args.warmup)
@@ -175,7 +176,8 @@ def run_single(args, wl):
                      n_conv / (ms / 1e3), ms, DTYPES[prec],
                      {"workload": wl.name, "samples": S, "robots": p.cfg.n_robots, "dims": p.cfg.dims,
                       "degree": p.cfg.degree, "horizon": p.cfg.horizon, "iters": K, "precision": prec,
-                      "kernel": "generic" if args.generic else "mfma", "graph": args.graph})
+                      "kernel": "generic" if args.generic else "mfma", "graph": args.graph,
+                      "launch_shape": "autotuned" if args.autotune else "plan default"})
     line.update({"converged_fraction": round(n_conv / S, 6), "violation_p99": p99, "violation_max": vmax,
                  "all_samples_per_s": round(S / (ms / 1e3), 1),
                  "roofline": roofline([(p.cfg, S)], K, ms, prec, traffic)})
@@ -265,6 +267,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--generic", action="store_true", help="force the generic (non-MFMA) kernel")
     ap.add_argument("--graph", action="store_true", help="replay the launch as a captured hipGraph")
+    ap.add_argument("--autotune", action="store_true",
+                    help="single-problem workloads: let the autotuner pick the launch shape (default: the plan's "
+                         "default shape; the ragged workload always autotunes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 3 device copies of 256 MiB (reference for the HBM byte counters)")
     args = ap.parse_args()

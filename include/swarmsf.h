@@ -63,7 +63,7 @@ typedef enum {
                                 argument set) and replay it; the first call must not be under capture */
 #define SF_AUTOTUNE 8        /* on the first call for a batch and precision (synchronizes): time the
                                 MFMA launch candidates (2, 3 or 4 waves per sample; for persistent launches
-                                also 1-6 workgroups per CU) on 30 iterations of this batch (best of two runs) and keep the
+                                also 1-6 workgroups per CU) on 50 (persistent: 30) iterations of this batch and keep the
                                 fastest, also in the JSON-lines cache $SWARMSF_TUNE_CACHE (default
                                 ~/.cache/swarmsf_tune.jsonl) for later processes */
 #define SF_PERSISTENT 16     /* run a single-shape batch through the persistent work-queue kernel (a

@@ -440,8 +440,12 @@ sf_status autotune(sf_handle h, const Plan* p, sf::FastPlan& fp, const sf::Launc
     grids.erase(std::unique(grids.begin(), grids.end()), grids.end());
     for (int g : grids) cand.push_back({W, g});
   }
+  // trial launches: single-shape plans are cheap, so they get longer trials, two warm-ups (the first
+  // launches of a kernel also grow its scratch backing) and the best of three; persistent plans
+  // over large ragged batches the best of two 30-iteration runs
   sf::LaunchArgs t = a;
-  t.iters = std::max(1, std::min(a.iters, 30));
+  t.iters = std::max(1, std::min(a.iters, fp.batched ? 30 : 50));
+  const int warm = fp.batched ? 1 : 2, reps = fp.batched ? 2 : 3;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(SF_EDEVICE, "events");
   auto run = [&](const std::pair<int, int>& c) {
@@ -451,9 +455,10 @@ sf_status autotune(sf_handle h, const Plan* p, sf::FastPlan& fp, const sf::Launc
   std::pair<int, int> best = cand[0];
   float best_ms = 1e30f;
   for (const auto& c : cand) {
-    hipError_t e = run(c);                                  // warm-up
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < warm && e == hipSuccess; ++i) e = run(c);
     float ms = 1e30f;
-    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // best of two timed runs
+    for (int rep = 0; rep < reps && e == hipSuccess; ++rep) {
       e = hipEventRecord(e0, a.stream);
       if (e == hipSuccess) e = run(c);
       if (e == hipSuccess) e = hipEventRecord(e1, a.stream);

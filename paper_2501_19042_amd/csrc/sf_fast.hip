@@ -1158,9 +1158,9 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
     const int64_t ni = (int64_t)items.size();
     for (int prec = SF_FP32; prec <= SF_FP16; ++prec) {
       const int mp = prec - SF_FP32;
-      // the most waves per workgroup that still lets every work item be resident at once;
-      // with more items than that, 4 (throughput over latency)
-      out.Wp[prec & 3] = ni <= slots(4, mp) ? 4 : (ni <= slots(3, mp) ? 3 : (ni <= slots(2, mp) ? 2 : 4));
+      // the most waves per workgroup that still lets every work item be resident at once; with
+      // more items than that, 2 (the most work items in flight)
+      out.Wp[prec & 3] = ni <= slots(4, mp) ? 4 : (ni <= slots(3, mp) ? 3 : 2);
     }
   }
   if (out.batched) {
