@@ -1,21 +1,23 @@
-// MFMA fast path of the safety filter for 3D swarms (n <= 32 robots, degree <= 15).
+// MFMA fast path of the safety filter for 3D swarms (n <= 32 robots, degree <= 15, H <= 256).
 //
-// One workgroup (W waves) owns one sample for the whole solve; xi, lambda and xi_bar stay in
-// LDS.  The horizon is cut into 16-step time tiles and wave w owns tiles w, w + W, ...
-// Per iteration and tile:
-//   S1  Y_b = P_b xi for the three bases (position, velocity, acceleration; eq. poly) as
-//       v_mfma_f32_16x16x4f32 products: rows = 16 times, columns = 16 robots of one axis.
-//       Lane (col, grp) ends up holding robot col at times 4 grp .. 4 grp + 3, all axes.
-//   S3  velocity/acceleration ball residuals in those registers (radial form of the d-step
-//       with d in [0, 1]).
-//   S2  collision residuals (alpha/beta/d steps in radial form): positions go to LDS, an exact
-//       broad phase drops every pair whose position boxes over the tile are farther apart than
-//       the safety distance (their residual is exactly zero), and the surviving pair-times are
-//       projected and scattered into an LDS accumulator.
-//   S4  g += P_b^T (rho_b R_b) as MFMA products, skipped for tiles whose residuals are all
-//       zero.  The S1 output layout is exactly the A-operand layout this product needs.
-// Then the multiplier step and the structured QP step of eq. (xi_step) on the free
-// coefficients, as in the generic kernel.
+// One workgroup (W = 2, 3 or 4 waves) owns one sample for the whole solve; xi, lambda and xi_bar
+// stay in LDS.  The horizon is cut into 16-step time tiles and wave w owns tiles w, w + W, ...
+// Per iteration (two workgroup barriers):
+//   tiles (each wave, no barrier)
+//     S1  Y_b = P_b xi for the bases (position, velocity, acceleration; eq. poly) as MFMA
+//         products (fp32, or bf16/fp16 with hi/lo correction terms): rows = 16 times, columns =
+//         16 robots of one axis; lane (col, grp) ends up holding robot col at times 4 grp + r.
+//     S3  velocity/acceleration ball residuals in those registers (radial form of the d-step
+//         with d in [0, 1]), skipped while a drift bound proves every ball inactive.
+//     S2  collision residuals (alpha/beta/d steps in radial form): positions go to LDS; per
+//         tile, a list of the pairs whose position boxes come within the safety distance plus a
+//         margin, rebuilt only when some robot may have moved by more than the margin; the
+//         listed pair-times are projected and scattered into an LDS accumulator.
+//     S4  g += P_b^T (rho_b R_b) as MFMA products, only for tiles with a nonzero residual; the
+//         S1 output layout is exactly the A-operand layout this product needs.
+//   barrier; tail (the 3 x 16R robot-axis rows, two lanes per row where they fit)
+//     multiplier step and the structured QP step of eq. (xi_step) on the free coefficients.
+//   barrier
 #include "sf_fast.h"
 
 #include <cfloat>
@@ -1000,8 +1002,8 @@ __global__ void reset_queue_kernel(int* queue, int n) {
 }
 
 // Kernel instances: R robot tiles of 16, KS k-steps of 4 coefficients, W waves per workgroup.
-constexpr int kW = 4;
-// Target waves per SIMD: the register budget that fits each instance without spills.
+// Target waves per SIMD (the register budget): 3 with one robot tile (168 VGPRs; three waves per
+// sample then keep four samples per CU resident), 1 with two (the whole register file).
 constexpr int waves_per_simd(int R, int MP) { return R == 1 ? 3 : 1; }
 
 FastArgs make_fast_args(const LaunchArgs& a, const float* tab32, const uint4* a16) {

@@ -132,3 +132,31 @@ def test_ragged_3000_full_size(P):
         e = ((g - rx).abs().reshape(take, -1).amax(1) / rx.abs().reshape(take, -1).amax(1)).numpy()
         print(f"ragged n={n} problem {k}: rel err {e}", flush=True)
         assert e.max() <= 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n", [16, 32])
+def test_every_launch_shape_matches_oracle(P, tmp_path, monkeypatch, prec, n):
+    """Each waves-per-sample choice (2, 3, 4), pinned through the autotuner's cache, solves the
+    same batch within the precision form's tolerance of the oracle."""
+    p = W.small3d(n_robots=n, n_samples=6, degree=10, horizon=100, seed=41 + n,
+                  box=((-3.0, -3.0, -1.0), (3.0, 3.0, 1.0)), t_final=10.0)
+    iters = 60
+    s = O.build_system(p.cfg)
+    rx, _, _ = O.sf_project(s, torch.tensor(p.xi_bar), torch.tensor(p.bvals), iters)
+    xb = torch.tensor(p.xi_bar, dtype=torch.float32).cuda()
+    bv = torch.tensor(p.bvals, dtype=torch.float32).cuda()
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("SWARMSF_TUNE_CACHE", str(cache))
+    P.SafetyFilter([p.cfg]).project(xb, bv, iters, precision=prec, autotune=True)
+    torch.cuda.synchronize()
+    key = [l for l in cache.read_text().splitlines() if '"key"' in l][-1].split('"key": "')[1].split('"')[0]
+    bound = 1e-4 if prec == "fp32" else 2e-3
+    for w in (2, 3, 4):
+        cache.write_text('{"key": "%s", "waves": %d, "grid": 0, "ms": 1.0}\n' % (key, w))
+        out = P.SafetyFilter([p.cfg]).project(xb, bv, iters, precision=prec, autotune=True)
+        torch.cuda.synchronize()
+        g = out.xi.cpu().double().reshape(6, -1)
+        e = ((g - rx.reshape(6, -1)).abs().amax(1) / rx.reshape(6, -1).abs().amax(1)).numpy()
+        print(f"n={n} {prec} W={w}: max rel err {e.max():.2e}", flush=True)
+        assert e.max() <= bound, (w, e)
