@@ -97,7 +97,7 @@ constexpr int kQPCols = 16;              // QP matrix row in LDS: both halves, e
 constexpr int kBoxRow = 12;
 constexpr int kHBRow = 20;
 struct FastLds {
-  int xi, lam, xb, xprev, dbar, corr, pairs, vmx, amx, dxi, qp, hb, tiles, per_wave, total;
+  int xi, lam, xb, xprev, dbar, corr, pairs, vmx, amx, dxi, cmx, qp, hb, tiles, per_wave, total;
   int xt, ct, bb, plist;   // offsets inside one wave's tile region
 };
 
@@ -116,6 +116,7 @@ __host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W, 
   p.vmx = o; o += W * nr;                  // per wave and robot: max ||v||^2 over the wave's tiles
   p.amx = o; o += W * nr;                  // same for the acceleration
   p.dxi = o; o += 3 * nr;                  // per (robot, axis): max |change| of a free coefficient
+  p.cmx = o; o += 3 * nr;                  // per (robot, axis): max |coefficient| of the iterate
   o = (o + 3) & ~3;
   p.qp = o; o += 2 * c.mf * kQPCols;       // X1, X01 transposed, rows of at most kQPCols floats
   o = (o + 3) & ~3;
@@ -174,6 +175,15 @@ __device__ __forceinline__ float group_sum(float v) {
     v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
   }
   return v;
+}
+
+// Maximum over the 64 lanes of a wave (all lanes active; every lane gets the result).
+__device__ __forceinline__ float wave_max(float v) {
+  v = fmaxf(v, dpp<0xB1>(v));
+  v = fmaxf(v, dpp<0x4E>(v));
+  v = fmaxf(v, dpp<0x141>(v));
+  v = fmaxf(v, dpp<0x140>(v));
+  return grp_max(v);
 }
 
 __device__ __forceinline__ void coll_resid3(float rx, float ry, float rz, float ia2, float ib2, float b,
@@ -277,6 +287,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
     float* s_vmx = smem + L.vmx;
     float* s_amx = smem + L.amx;
     float* s_dxi = smem + L.dxi;
+    float* s_cmx = smem + L.cmx;
     // 16-bit hi/lo split of xi in the S1 B-operand layout, kept current by whoever writes xi
     typedef typename Half<MP == 0 ? 1 : MP>::E HE;
     HE* shb = reinterpret_cast<HE*>(smem + L.hb);
@@ -338,6 +349,15 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
       for (int q = tid; q < 3 * NR; q += nthr) s_dxi[q] = 0.0f;
       for (int q = lane; q < 3 * NR * 16; q += 64) Ct[q] = 0.0f;
       __syncthreads();
+      // per-row bound on |coefficient| over the iterates: the initial one and the pinned values
+      for (int q = tid; q < 3 * NR; q += nthr) {
+        float cm = 0.0f;
+        if (q < 3 * n) {
+          for (int kk = 0; kk < m; ++kk) cm = fmaxf(cm, fabsf(sxi[q * m + kk]));
+          for (int r = 0; r < kNFix; ++r) cm = fmaxf(cm, fabsf(pinned(q, r)));
+        }
+        s_cmx[q] = cm;
+      }
       if constexpr (MP != 0) {
         // one thread per (axis, robot, coefficient) of the padded operand rows (zeros outside)
         for (int q = tid; q < 3 * NR * 16; q += nthr) {
@@ -398,27 +418,31 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         // and S1/S3/S4 for that basis are skipped.  Iterations 0 and 1 always evaluate (the pinned
         // coefficients change in the first step).
         int eval_flags = 3;
+        float cm;   // bound on |coefficient| of robot `lane` over the iterates so far
         {
           float dn = 0.0f;
+          cm = 0.0f;
           if (lane < n) {
             // margins to the bounds measured by the previous iteration if it evaluated them
-            // (every wave computes the same values)
+            // (every wave computes the same values).  The hardware square root (1 ulp) serves: the
+            // test below keeps a 1e-4 relative slack, far above its error.
             if (prev_eval & 1) {
               float mx = 0.0f;
 #pragma unroll
               for (int ww = 0; ww < W; ++ww) mx = fmaxf(mx, s_vmx[ww * NR + lane]);
-              mv = vmax - sqrtf(mx);
+              mv = vmax - __builtin_amdgcn_sqrtf(mx);
               dv = 0.0f;
             }
             if (prev_eval & 2) {
               float mx = 0.0f;
 #pragma unroll
               for (int ww = 0; ww < W; ++ww) mx = fmaxf(mx, s_amx[ww * NR + lane]);
-              ma = amax - sqrtf(mx);
+              ma = amax - __builtin_amdgcn_sqrtf(mx);
               da = 0.0f;
             }
             const float d0 = s_dxi[lane * 3], d1 = s_dxi[lane * 3 + 1], d2 = s_dxi[lane * 3 + 2];
-            dn = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+            cm = fmaxf(fmaxf(s_cmx[lane * 3], s_cmx[lane * 3 + 1]), s_cmx[lane * 3 + 2]);
+            dn = __builtin_amdgcn_sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
             px_ += d0;
             py_ += d1;
             pz_ += d2;
@@ -434,6 +458,18 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         // built with (and in iterations 0 and 1, where the pinned coefficients jump).
         const bool rebuild = k < 2 || ballot(lane < n && (px_ > skx || py_ > skx || pz_ > skz)) != 0;
         if (rebuild) px_ = py_ = pz_ = 0.0f;
+        // Margins of the broad phase: twice the drift margin per axis, plus the rounding of the
+        // positions.  A computed position is a rounded convex combination of its coefficients, off by
+        // at most ~1.2e-5 of the largest |coefficient| (16-bit split products; fp32 far less); 2^-12
+        // of a bound on that over the sample (running maximum, plus the most the coefficients can
+        // grow before the next rebuild) holds for both robots of a pair in the build and every reuse
+        // iteration.
+        float mgx = 0.0f, mgz = 0.0f;
+        if (rebuild) {
+          const float tol = 2.44140625e-4f * (wave_max(cm) + fmaxf(skx, skz));
+          mgx = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(2.0f * skx + tol)));
+          mgz = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(2.0f * skz + tol)));
+        }
         // S1 B operand: xi^T, lane (col, grp) holds robot col, coefficient 4 s + grp
         float bx[MP == 0 ? R : 1][3][KS];
         typename Half<MP == 0 ? 1 : MP>::V hb1[MP == 0 ? 1 : R][3], hb2[MP == 0 ? 1 : R][3];
@@ -518,6 +554,13 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           const int nt = min(16, H - t0);
           const float4 ca = pa, cb = pb;
           const uint4 cu1 = pu1, cu2 = pu2;
+          // narrow-phase lane mapping: lanes cover (pair, time) items, 64 / T pairs per round with
+          // T = the tile's valid times rounded up to 4, 8 or 16.  A list kept from an earlier
+          // iteration is read now (count and first round together), ahead of the products.
+          int* tl = reinterpret_cast<int*>(wbuf + L.plist) + q * (NR * (NR - 1) / 2 + 1);
+          const int tsh = nt <= 4 ? 2 : (nt <= 8 ? 3 : 4);
+          const int tt = lane & ((1 << tsh) - 1), ps = lane >> tsh, ppr = 64 >> tsh;
+          const int kept_count = tl[0], kept_first = tl[1 + ps];
           if (tau + W < NT) {
             const int nx = tau + W;
             if constexpr (MP == 0) pa = a32c[((nx * 3) * 2) * 64 + lane];
@@ -573,7 +616,8 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                 const float vx = Y[rr][0][r], vy = Y[rr][1][r], vz = Y[rr][2][r];
                 const float ss = vx * vx + vy * vy + vz * vz;
                 mx = fmaxf(mx, ss);
-                const float f = ss > lim * lim ? 1.0f - lim * rsqrtf(ss) : 0.0f;
+                // (ss > lim^2 is a normal number, so the bare hardware rsqrt serves)
+                const float f = ss > lim * lim ? 1.0f - lim * __builtin_amdgcn_rsqf(ss) : 0.0f;
                 Y[rr][0][r] = f * vx;
                 Y[rr][1][r] = f * vy;
                 Y[rr][2][r] = f * vz;
@@ -594,12 +638,12 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           }
           wave_sync();
           // ---- S2: broad phase over the tile (when the lists are rebuilt), narrow phase on the list ----
-          // A pair is listed when its boxes, shrunk by twice the margin per axis, are closer than the
+          // A pair is listed when its boxes, each gap shrunk by the margins above, are closer than the
           // safety distance (scaled, 1e-4 relative slack); until the next rebuild no unlisted pair can
           // come closer than the safety distance, so its residual is exactly zero.
           // (unused lanes test the pair (0, 1) and discard the result, so all box loads issue at once)
-          int* tl = reinterpret_cast<int*>(wbuf + L.plist) + q * (NR * (NR - 1) / 2 + 1);
           int count = 0;
+          int pnext = 0;
           if (rebuild) {
           bool act[PR];
 #pragma unroll
@@ -613,10 +657,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             float g2 = 0.0f;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-              // the list is reused on later iterations' positions, whose rounding differs from these
-              // by a few 1e-5 of the coordinates at most (16-bit split products): 2^-12 covers it
-              const float tol = 2.44140625e-4f * fmaxf(fmaxf(fabsf(li[d]), fabsf(hi[d])), fmaxf(fabsf(lj[d]), fabsf(hj[d])));
-              const float gap = fmaxf(0.0f, fmaxf(lj[d] - hi[d], li[d] - hj[d]) - 2.0f * (d == 2 ? skz : skx) - tol);
+              const float gap = fmaxf(0.0f, fmaxf(lj[d] - hi[d], li[d] - hj[d]) - (d == 2 ? mgz : mgx));
               g2 += gap * gap * (d == 2 ? ib2 : ia2);
             }
             act[r] = mypair[r] >= 0 && g2 < 1.0001f;
@@ -630,15 +671,14 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           }
           if (lane == 0) tl[0] = count;
           wave_sync();
+          pnext = ps < count ? tl[1 + ps] : 0;
           } else {
-            count = __builtin_amdgcn_readfirstlane(tl[0]);
+            count = __builtin_amdgcn_readfirstlane(kept_count);
+            pnext = ps < count ? kept_first : 0;
           }
-          // narrow phase: lanes cover (pair, time) items, 64 / T pairs per round with T = the tile's
-          // valid times rounded up to 4, 8 or 16; the next round's pair codes load meanwhile
-          const int tsh = nt <= 4 ? 2 : (nt <= 8 ? 3 : 4);
-          const int tt = lane & ((1 << tsh) - 1), ps = lane >> tsh, ppr = 64 >> tsh;
+          // narrow phase, one round of pairs per step; the next round's pair codes load meanwhile
+          // (most tiles list at most one round)
           bool nzc = false;
-          int pnext = ps < count ? tl[1 + ps] : 0;
           for (int base = 0; base < count; base += ppr) {
             const int slot = base + ps;
             const int pij = pnext;
@@ -705,60 +745,86 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         // With HALVES = 2 a row is owned by two lanes 32 apart in one wave, each taking half of its
         // free and pinned coefficients; they swap their halves of y and mean(y) for the QP product.
         // Rows are axis-major, so the robots of one axis sit in aligned groups of 16R lanes.
-        // Loads use clamped (always valid) addresses and only the stores are guarded, so that all
-        // loads of a step issue back to back.
-        const float* gp0 = smem + L.tiles;
-        auto gsum = [&](int q) {
-          float g = 0.0f;
-#pragma unroll
-          for (int ww = 0; ww < W; ++ww) g += gp0[ww * L.per_wave + q];
-          return g;
-        };
+        // Every load of the step is issued first, from clamped (always valid) addresses, and a
+        // scheduling barrier keeps the arithmetic after them, so the step waits for LDS once; y is
+        // zero past the free coefficients, so the QP product needs no guard either.
         if (wave < TAILW) {
+          const float* gp0 = smem + L.tiles;
           const int hl = HALVES == 2 ? (lane >> 5) : 0;
           const int trow = wave * (64 / HALVES) + (HALVES == 2 ? (lane & 31) : lane);
           const int ax = trow / NR, rb = trow - ax * NR;
           const bool on = ax < 3 && rb < n;
           const int row = on ? rb * 3 + ax : 0;
-          // pinned coefficients of the row: multiplier step, and their boundary values in step 0
-          constexpr int PF = kNFix / HALVES;
-          float nl[PF];
+          constexpr int PF = kNFix / HALVES;                  // pinned coefficients per lane
+          constexpr int QD = FHP > 4 ? 1 : 2;                 // QP rows loaded ahead of their use
           int qq[PF];
+          float lp[PF], gr[PF + FH][W], xv[FH], lf[FH], xb[FH], cr[FH];
+          f4 qa[QD][FHP / 4], qb[QD][FHP / 4];
+          auto qp_row = [&](int f2, f4 (&a1)[FHP / 4], f4 (&a2)[FHP / 4]) {
+            const int rc = max(0, min(f2, mf - 1));
+#pragma unroll
+            for (int cc = 0; cc < FHP / 4; ++cc) {
+              a1[cc] = *reinterpret_cast<const f4*>(sX1 + ((0 * HALVES + hl) * mf + rc) * FHP + 4 * cc);
+              a2[cc] = *reinterpret_cast<const f4*>(sX1 + ((1 * HALVES + hl) * mf + rc) * FHP + 4 * cc);
+            }
+          };
 #pragma unroll
           for (int j = 0; j < PF; ++j) {
             qq[j] = row * m + fixed_k(hl * PF + j);
-            nl[j] = slam[qq[j]] - gsum(qq[j]);
+            lp[j] = slam[qq[j]];
+#pragma unroll
+            for (int ww = 0; ww < W; ++ww) gr[j][ww] = gp0[ww * L.per_wave + qq[j]];
           }
+#pragma unroll
+          for (int j = 0; j < FH; ++j) {
+            const int fc = max(0, min(hl * FH + j, mf - 1));
+            const int q = row * m + 3 + fc;
+            xv[j] = sxi[q];
+            lf[j] = slam[q];
+            xb[j] = sxb[q];
+            cr[j] = scorr[row * (mf > 0 ? mf : 1) + fc];
+#pragma unroll
+            for (int ww = 0; ww < W; ++ww) gr[PF + j][ww] = gp0[ww * L.per_wave + q];
+          }
+          float cmax = s_cmx[row];   // running bound on |coefficient| of the row (pinned values included)
+#pragma unroll
+          for (int f2 = 0; f2 < QD; ++f2) qp_row(f2, qa[f2], qb[f2]);
+          __builtin_amdgcn_sched_barrier(0);
+          auto gsum = [&](int j) {
+            float g = gr[j][0];
+#pragma unroll
+            for (int ww = 1; ww < W; ++ww) g += gr[j][ww];
+            return g;
+          };
+          // pinned coefficients: multiplier step (their boundary values are set in step 0 below)
+          float nl[PF];
+#pragma unroll
+          for (int j = 0; j < PF; ++j) nl[j] = lp[j] - gsum(j);
           // free coefficients f = hl * FH + j
-          float yo[FH], ln[FH], xv[FH];
+          float yo[FH], ln[FH];
 #pragma unroll
           for (int j = 0; j < FH; ++j) {
             const int f = hl * FH + j;
-            const int fc = max(0, min(f, mf - 1));
-            const int q = row * m + 3 + fc;
-            const float g = gsum(q);
-            xv[j] = sxi[q];
-            ln[j] = slam[q] - g;
-            float yv = sxb[q] - xv[j] + ln[j] - g;
-            if (k == 0) yv += scorr[row * (mf > 0 ? mf : 1) + fc];
+            const float g = gsum(PF + j);
+            ln[j] = lf[j] - g;
+            float yv = xb[j] - xv[j] + ln[j] - g;
+            if (k == 0) yv += cr[j];
             yo[j] = (on && f < mf) ? yv : 0.0f;
           }
           float ybo[FH];
 #pragma unroll
           for (int j = 0; j < FH; ++j) ybo[j] = group_sum<NR>(yo[j]) * inv_n;
-          // all free coefficients' y and mean(y), in order
+          // all free coefficients' y and mean(y), in order (zero past mf)
           float ya[HALVES * FH], yba[HALVES * FH];
 #pragma unroll
           for (int j = 0; j < FH; ++j) {
             if constexpr (HALVES == 2) {
               const auto sy = __builtin_amdgcn_permlane32_swap(__float_as_uint(yo[j]), __float_as_uint(yo[j]), false, false);
               const auto sb2 = __builtin_amdgcn_permlane32_swap(__float_as_uint(ybo[j]), __float_as_uint(ybo[j]), false, false);
-              const float y0 = __uint_as_float(sy[0]), y1 = __uint_as_float(sy[1]);     // halves 0, 1
-              const float b0 = __uint_as_float(sb2[0]), b1 = __uint_as_float(sb2[1]);
-              ya[j] = y0;
-              ya[FH + j] = y1;
-              yba[j] = b0;
-              yba[FH + j] = b1;
+              ya[j] = __uint_as_float(sy[0]);        // half 0
+              ya[FH + j] = __uint_as_float(sy[1]);   // half 1
+              yba[j] = __uint_as_float(sb2[0]);
+              yba[FH + j] = __uint_as_float(sb2[1]);
             } else {
               ya[j] = yo[j];
               yba[j] = ybo[j];
@@ -768,32 +834,30 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           float acc[FHP];
 #pragma unroll
           for (int j = 0; j < FHP; ++j) acc[j] = 0.0f;
+          // (rows QD ahead are loaded as each row is used; the barriers keep that order)
 #pragma unroll
-          for (int f2 = 0; f2 < HALVES * FH; ++f2) {
-            if (f2 < MFX) {
-              const int rc = max(0, min(f2, mf - 1));
-              f4 a1[FHP / 4], a2[FHP / 4];
+          for (int f2 = 0; f2 < MFX; ++f2) {
+            const int sl = f2 % QD;
 #pragma unroll
-              for (int cc = 0; cc < FHP / 4; ++cc) {
-                a1[cc] = *reinterpret_cast<const f4*>(sX1 + ((0 * HALVES + hl) * mf + rc) * FHP + 4 * cc);
-                a2[cc] = *reinterpret_cast<const f4*>(sX1 + ((1 * HALVES + hl) * mf + rc) * FHP + 4 * cc);
-              }
-              if (f2 < mf) {
-#pragma unroll
-                for (int j = 0; j < FHP; ++j) {
-                  acc[j] = fmaf(a1[j / 4][j % 4], ya[f2], acc[j]);
-                  acc[j] = fmaf(a2[j / 4][j % 4], yba[f2], acc[j]);
-                }
-              }
+            for (int j = 0; j < FHP; ++j) {
+              acc[j] = fmaf(qa[sl][j / 4][j % 4], ya[f2], acc[j]);
+              acc[j] = fmaf(qb[sl][j / 4][j % 4], yba[f2], acc[j]);
             }
+            if (f2 + QD < MFX) qp_row(f2 + QD, qa[sl], qb[sl]);
+            __builtin_amdgcn_sched_barrier(0);
           }
           float dmax = 0.0f;
 #pragma unroll
           for (int j = 0; j < FH; ++j)
-            if (hl * FH + j < mf) dmax = fmaxf(dmax, fabsf(acc[j]));
+            if (hl * FH + j < mf) {
+              dmax = fmaxf(dmax, fabsf(acc[j]));
+              cmax = fmaxf(cmax, fabsf(xv[j] + acc[j]));
+            }
           if constexpr (HALVES == 2) {
             const auto sd = __builtin_amdgcn_permlane32_swap(__float_as_uint(dmax), __float_as_uint(dmax), false, false);
             dmax = fmaxf(__uint_as_float(sd[0]), __uint_as_float(sd[1]));
+            const auto sc = __builtin_amdgcn_permlane32_swap(__float_as_uint(cmax), __float_as_uint(cmax), false, false);
+            cmax = fmaxf(__uint_as_float(sc[0]), __uint_as_float(sc[1]));
           }
           if (on) {
 #pragma unroll
@@ -815,7 +879,10 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                 if constexpr (MP != 0) put_split(rb, ax, 3 + f, xn);
               }
             }
-            if (hl == 0) s_dxi[row] = dmax;
+            if (hl == 0) {
+              s_dxi[row] = dmax;
+              s_cmx[row] = cmax;   // (the other half read it above, in the same wave)
+            }
           }
         }
         __syncthreads();
