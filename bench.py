@@ -115,7 +115,7 @@ def time_calls(call, steps, warmup):
 
 def judge(sf, out_xi, bv, prec, batch=None):
     viol = sf.feasibility(out_xi, bv, batch=batch, precision=prec).cpu()
-    worst = viol[:, :3].amax(1).clamp_min(viol[:, 3])
+    worst = viol.amax(1)   # collision, velocity, acceleration, boundary, workspace
     feas = worst <= FEAS_TOL
     return int(feas.sum()), float(worst.quantile(0.99)), float(worst.max())
 

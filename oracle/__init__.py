@@ -12,6 +12,7 @@ from .sf_oracle import (  # noqa: F401
     build_system,
     project_collision,
     project_ball,
+    project_workspace,
     sf_project,
     feasibility,
     to_paper_order,

@@ -19,6 +19,9 @@ Readings of the paper taken here, where it is silent, ambiguous or garbled:
     angle in the axis-scaled frame (the paper cites closed forms it does not print).
   * velocity/acceleration bounds are not in the paper; they are modelled as
     origin-centred balls in the polar form of eq. (workspace_polar), d in [0, 1].
+  * the workspace constraint (eqs. (workspace_con), (workspace_polar)) is off unless
+    its semi-axes are given; its angles are those of the axis-scaled offset from the
+    centre, as for the collision spheroid.
   * polynomial basis: Bernstein of the given degree on tau = t/T, uniform grid
     tau_h = h/(H-1) including both endpoints.
   * goal boundary conditions are (p, v, a) at t = T (eq. (boundary_con) lists the
@@ -115,6 +118,10 @@ class OracleSystem:
     n_pairs: int
     vel_on: bool
     acc_on: bool
+    ws_on: bool = False
+    ws_a: float = 0.0
+    ws_b: float = 0.0
+    ws_c: Optional[torch.Tensor] = None    # workspace centre [D]
 
     @property
     def nm(self) -> int:
@@ -142,6 +149,12 @@ def build_system(cfg) -> OracleSystem:
     if acc_on:
         rows.append(torch.kron(eye_n, Pdd))
         w.append(torch.full((n * H,), float(cfg.rho_acc), dtype=DT))
+    ws_a, ws_b = float(getattr(cfg, "ws_a", 0.0)), float(getattr(cfg, "ws_b", 0.0))
+    ws_on = ws_a > 0
+    if ws_on:
+        # workspace rows, eq. (workspace_con): every robot position at every grid time
+        rows.append(torch.kron(eye_n, P))
+        w.append(torch.full((n * H,), float(cfg.rho_ws), dtype=DT))
     F = torch.cat(rows, dim=0)
     w = torch.cat(w)
     A1 = torch.stack([P[0], Pd[0], Pdd[0], P[H - 1], Pd[H - 1], Pdd[H - 1]])
@@ -155,7 +168,10 @@ def build_system(cfg) -> OracleSystem:
     return OracleSystem(n=n, D=D, m=m, H=H, a=float(cfg.safety_a), b=float(cfg.safety_b),
                         vmax=float(cfg.vmax), amax=float(cfg.amax), P=P, Pd=Pd, Pdd=Pdd,
                         F=F, w=w, A=A, kkt_lu=lu, n_pairs=Dp.shape[0],
-                        vel_on=vel_on, acc_on=acc_on)
+                        vel_on=vel_on, acc_on=acc_on, ws_on=ws_on, ws_a=ws_a,
+                        ws_b=ws_b if ws_on else 0.0,
+                        ws_c=torch.tensor([float(getattr(cfg, k, 0.0)) for k in ("ws_x", "ws_y", "ws_z")][:D],
+                                          dtype=DT))
 
 
 # ---------------------------------------------------------------------------
@@ -208,6 +224,13 @@ def project_ball(v: torch.Tensor, radius: float) -> torch.Tensor:
     return _polar_target(v, radius, radius, 0.0, 1.0)
 
 
+def project_workspace(p: torch.Tensor, a: float, b: float, centre=None) -> torch.Tensor:
+    """Targets for the workspace rows (the F_w block of eq. (f_e)): p_w + d u(alpha_w, beta_w)
+    with the spheroid (a, a, b) of eq. (workspace_polar), d in [0, 1]."""
+    c = torch.zeros(p.shape[-1], dtype=DT) if centre is None else torch.as_tensor(centre, dtype=DT)
+    return c + _polar_target(p - c, a, b, 0.0, 1.0)
+
+
 def _targets(sys: OracleSystem, Y: torch.Tensor) -> torch.Tensor:
     """e for all rows of all axes.  Y = F xi per axis: [B, D, rows] -> e of the same shape."""
     B, D, _ = Y.shape
@@ -224,6 +247,11 @@ def _targets(sys: OracleSystem, Y: torch.Tensor) -> torch.Tensor:
         v = Y[:, :, o:o + n * H].reshape(B, D, n, H).permute(0, 2, 3, 1)        # [B, n, H, D]
         ev = project_ball(v, lim)
         parts.append(ev.permute(0, 3, 1, 2).reshape(B, D, n * H))
+        o += n * H
+    if sys.ws_on:
+        p = Y[:, :, o:o + n * H].reshape(B, D, n, H).permute(0, 2, 3, 1)        # [B, n, H, D]
+        ep = project_workspace(p, sys.ws_a, sys.ws_b, sys.ws_c)
+        parts.append(ep.permute(0, 3, 1, 2).reshape(B, D, n * H))
         o += n * H
     return torch.cat(parts, dim=2)
 
@@ -286,9 +314,10 @@ def _resid_pair(sys: OracleSystem, rp: torch.Tensor) -> torch.Tensor:
 
 
 def feasibility(sys: OracleSystem, xi: torch.Tensor, bvals: torch.Tensor) -> torch.Tensor:
-    """Constraint violations at the grid times, [B, 4] float64:
+    """Constraint violations at the grid times, [B, 5] float64:
     (collision: a * (1 - min ||M_a^{-1}(p_i - p_j)||), max ||v|| - vmax, max ||acc|| - amax,
-     max |A xi - b|).  Positive means violated."""
+     max |A xi - b|, workspace: a_w * (max ||M_w^{-1} p_i|| - 1), 0 when it is off).
+    Positive means violated."""
     xi = xi.to(DT)
     X = torch.einsum("hk,bidk->bidh", sys.P, xi)
     V = torch.einsum("hk,bidk->bidh", sys.Pd, xi)
@@ -305,4 +334,12 @@ def feasibility(sys: OracleSystem, xi: torch.Tensor, bvals: torch.Tensor) -> tor
     acc = Acc.pow(2).sum(2).sqrt().amax(dim=(1, 2)) - sys.amax
     A1 = sys.A[:6, :sys.m]
     bnd = (torch.einsum("rk,bidk->bidr", A1, xi) - bvals.to(DT)[None]).abs().amax(dim=(1, 2, 3))
-    return torch.stack([coll, vel, acc, bnd], dim=1)
+    if sys.ws_on:
+        sw = torch.full((sys.D,), sys.ws_a, dtype=DT)
+        if sys.D == 3:
+            sw[2] = sys.ws_b
+        q = ((X - sys.ws_c[None, None, :, None]) / sw[None, None, :, None]).pow(2).sum(2).sqrt()
+        ws = sys.ws_a * (q.amax(dim=(1, 2)) - 1.0)
+    else:
+        ws = torch.zeros_like(bnd)
+    return torch.stack([coll, vel, acc, bnd, ws], dim=1)

@@ -42,7 +42,10 @@ def test_oracle_reproduces_golden(path):
     assert ((lam - g["lam"]).abs() / (1 + g["lam"].abs())).max() < 1e-11
     assert torch.allclose(resid, g["resid"], rtol=1e-8, atol=1e-14)
     viol = O.feasibility(s, xi, g["bvals"])
-    assert torch.allclose(viol, g["viol"], rtol=1e-8, atol=1e-12)
+    nv = g["viol"].shape[1]           # fixtures without the workspace hold its first 4 columns
+    assert torch.allclose(viol[:, :nv], g["viol"], rtol=1e-8, atol=1e-12)
+    if not s.ws_on:
+        assert (viol[:, 4] == 0).all()
 
 
 @pytest.mark.gpu
@@ -60,7 +63,8 @@ def test_gpu_fp64_matches_golden(path):
         assert err <= 1e-9, f"{name} {k}: {err:.3e}"
     assert torch.allclose(out.resid.cpu(), g["resid"], rtol=1e-7, atol=1e-12)
     viol = sf.feasibility(out.xi, g["bvals"].cuda(), precision="fp64").cpu()
-    assert torch.allclose(viol, g["viol"], rtol=1e-6, atol=1e-9)
+    nv = g["viol"].shape[1]
+    assert torch.allclose(viol[:, :nv], g["viol"], rtol=1e-6, atol=1e-9)
 
 
 @pytest.mark.gpu

@@ -8,6 +8,8 @@ in the oracle fails at least one of them.
 import math
 from fractions import Fraction
 
+from dataclasses import replace
+
 import numpy as np
 import pytest
 import scipy.linalg
@@ -47,9 +49,10 @@ def curve_on_grid(xi, H, T):
     return X, V, A
 
 
-def independent_F(n, P, Pd, Pdd, vel=True, acc=True):
+def independent_F(n, P, Pd, Pdd, vel=True, acc=True, ws=False):
     """One axis block of F built row by row: pair (i<j) rows are P at robot i and -P at
-    robot j; then velocity and acceleration rows per robot."""
+    robot j; then velocity and acceleration rows per robot; then (ws) position rows per
+    robot for the workspace (the F_w block of eq. (f_e))."""
     H, m = P.shape
     rows = []
     for i in range(n):
@@ -58,7 +61,7 @@ def independent_F(n, P, Pd, Pdd, vel=True, acc=True):
             blk[:, i * m:(i + 1) * m] = P
             blk[:, j * m:(j + 1) * m] = -P
             rows.append(blk)
-    for on, M in ((vel, Pd), (acc, Pdd)):
+    for on, M in ((vel, Pd), (acc, Pdd), (ws, P)):
         if on:
             for i in range(n):
                 blk = np.zeros((H, n * m))
@@ -79,10 +82,12 @@ def closest_point_inside(v, R):
     return np.where(nv <= R, v, R * v / np.maximum(nv, 1e-300))
 
 
-def small_cfg(n=3, D=3, degree=7, H=12, T=4.0, a=0.3, vmax=1.5, amax=2.0, rho=(1.0, 1.0, 1.0)):
+def small_cfg(n=3, D=3, degree=7, H=12, T=4.0, a=0.3, vmax=1.5, amax=2.0, rho=(1.0, 1.0, 1.0),
+              ws=(0.0, 0.0), rho_ws=1.0, ws_c=(0.0, 0.0, 0.0)):
     return W.SwarmConfig(n_robots=n, dims=D, degree=degree, horizon=H, t_final=T,
                          safety_a=a, safety_b=a, vmax=vmax, amax=amax,
-                         rho_coll=rho[0], rho_vel=rho[1], rho_acc=rho[2])
+                         rho_coll=rho[0], rho_vel=rho[1], rho_acc=rho[2],
+                         ws_a=ws[0], ws_b=ws[1], rho_ws=rho_ws, ws_x=ws_c[0], ws_y=ws_c[1], ws_z=ws_c[2])
 
 
 # --------------------------------------------------------------------------
@@ -164,6 +169,12 @@ def test_F_matches_row_by_row_construction():
     s = O.build_system(cfg)
     Fi = independent_F(4, s.P.numpy(), s.Pd.numpy(), s.Pdd.numpy())
     assert np.array_equal(s.F.numpy(), Fi)
+    # with the workspace rows (eq. (f_e)): block diagonal P after the bound rows, weighted rho_ws
+    cfg = small_cfg(n=4, D=3, degree=8, H=9, ws=(2.0, 1.0), rho_ws=0.6)
+    s = O.build_system(cfg)
+    Fi = independent_F(4, s.P.numpy(), s.Pd.numpy(), s.Pdd.numpy(), ws=True)
+    assert np.array_equal(s.F.numpy(), Fi)
+    assert np.array_equal(s.w.numpy()[-4 * 9:], np.full(4 * 9, 0.6))
 
 
 # --------------------------------------------------------------------------
@@ -230,6 +241,33 @@ def test_spheroid_target_is_radial_projection_in_scaled_frame():
     assert np.allclose(e, expect, atol=1e-13)
 
 
+def test_workspace_target_is_radial_projection_in_scaled_frame():
+    # eq. (workspace_polar) about the centre p_w: with the least-squares d = ||s||, s = M_w^{-1}
+    # (p - p_w), the target is p_w + M_w s min(1, 1/||s||): points inside stay, points outside
+    # are scaled back onto the spheroid along the ray from the centre in the scaled frame
+    rng = np.random.default_rng(14)
+    a, b = 2.0, 0.7
+    c = np.array([0.5, -0.25, 0.3])
+    p = c + rng.normal(size=(800, 3)) * np.array([2.0, 2.0, 0.8])
+    e = O.project_workspace(torch.tensor(p), a, b, torch.tensor(c)).numpy()
+    Mi = np.array([1 / a, 1 / a, 1 / b])
+    s_ = (p - c) * Mi
+    ns = np.linalg.norm(s_, axis=1, keepdims=True)
+    expect = c + (s_ * np.minimum(1.0, 1.0 / ns)) / Mi
+    assert np.allclose(e, expect, atol=1e-13)
+    inside = ns[:, 0] <= 1.0
+    assert inside.any() and (~inside).any()
+    assert np.allclose(e[inside], p[inside], atol=1e-15)
+    # on a ball (a = b) it is the closest point inside, in 2D and 3D; the centre maps to itself
+    for D in (2, 3):
+        q = rng.normal(size=(500, D)) * 1.5
+        cc = c[:D]
+        e2 = O.project_workspace(torch.tensor(cc + q), 1.2, 1.2, torch.tensor(cc)).numpy()
+        assert np.allclose(e2, cc + closest_point_inside(q, 1.2), atol=1e-13)
+        e0 = O.project_workspace(torch.tensor(cc[None]), 1.2, 1.2, torch.tensor(cc)).numpy()
+        assert np.allclose(e0, cc[None], atol=0)
+
+
 def test_coincident_robots_tie_break():
     # atan2(0, 0) = 0: alpha = beta = 0, so the target is (0, 0, b) in 3D and (a, 0) in 2D
     e3 = O.project_collision(torch.zeros(1, 3, dtype=DT), 0.3, 0.4).numpy()[0]
@@ -246,13 +284,18 @@ def test_coincident_robots_tie_break():
 
 def _one_step_independent(cfg, xi_bar, bvals, xi0, lam0):
     """Projection by closest points, lambda step with the minus sign, and the xi step as
-    an equality-constrained least squares solved on the null space of A (scipy)."""
+    an equality-constrained least squares solved on the null space of A (scipy).  A
+    workspace, if any, must be a ball (a_w = b_w), whose projection is the closest point."""
     s = O.build_system(cfg)
     n, D, m, H = cfg.n_robots, cfg.dims, cfg.degree + 1, cfg.horizon
     P, Pd, Pdd = s.P.numpy(), s.Pd.numpy(), s.Pdd.numpy()
-    F = independent_F(n, P, Pd, Pdd)
+    ws = cfg.ws_a > 0
+    assert not ws or cfg.ws_a == cfg.ws_b
+    F = independent_F(n, P, Pd, Pdd, ws=ws)
     Np = n * (n - 1) // 2
-    w = np.concatenate([np.full(Np * H, cfg.rho_coll), np.full(n * H, cfg.rho_vel), np.full(n * H, cfg.rho_acc)])
+    w = np.concatenate([np.full(Np * H, cfg.rho_coll), np.full(n * H, cfg.rho_vel), np.full(n * H, cfg.rho_acc)]
+                       + ([np.full(n * H, cfg.rho_ws)] if ws else []))
+    wc = np.array([cfg.ws_x, cfg.ws_y, cfg.ws_z])[:D]
     A1 = np.stack([P[0], Pd[0], Pdd[0], P[-1], Pd[-1], Pdd[-1]])
     A = np.kron(np.eye(n), A1)
     out_xi = np.zeros_like(xi0)
@@ -262,7 +305,9 @@ def _one_step_independent(cfg, xi_bar, bvals, xi0, lam0):
         E = np.empty_like(Y)
         E[:Np * H] = closest_point_outside(Y[:Np * H], cfg.safety_a)
         E[Np * H:Np * H + n * H] = closest_point_inside(Y[Np * H:Np * H + n * H], cfg.vmax)
-        E[Np * H + n * H:] = closest_point_inside(Y[Np * H + n * H:], cfg.amax)
+        E[Np * H + n * H:Np * H + 2 * n * H] = closest_point_inside(Y[Np * H + n * H:Np * H + 2 * n * H], cfg.amax)
+        if ws:
+            E[Np * H + 2 * n * H:] = wc + closest_point_inside(Y[Np * H + 2 * n * H:] - wc, cfg.ws_a)
         for d in range(D):
             lam = lam0[bidx, :, d, :].reshape(-1) - F.T @ (w * (Y[:, d] - E[:, d]))
             target = xi_bar[bidx, :, d, :].reshape(-1) + lam
@@ -278,9 +323,12 @@ def _one_step_independent(cfg, xi_bar, bvals, xi0, lam0):
     return out_xi, out_lam
 
 
-@pytest.mark.parametrize("D", [2, 3])
-def test_one_iteration_matches_independent_step(D):
-    cfg = small_cfg(n=3, D=D, degree=7, H=12, rho=(1.0, 0.7, 1.3))
+@pytest.mark.parametrize("D,ws", [(2, False), (3, False), (2, True), (3, True)])
+def test_one_iteration_matches_independent_step(D, ws):
+    # with the workspace: a ball of radius 0.35 about an off-origin centre, so that part of
+    # every trajectory lies outside it
+    cfg = small_cfg(n=3, D=D, degree=7, H=12, rho=(1.0, 0.7, 1.3),
+                    ws=(0.35, 0.35) if ws else (0.0, 0.0), rho_ws=0.8, ws_c=(0.05, -0.1, 0.02))
     rng = np.random.default_rng(5)
     st = rng.uniform(-0.4, 0.4, size=(3, D))
     gl = -st
@@ -314,13 +362,34 @@ def _feasible_line_instance(n=4, D=3):
     return cfg, xi, b
 
 
-def test_feasible_input_is_a_fixed_point():
+@pytest.mark.parametrize("ws", [False, True])
+def test_feasible_input_is_a_fixed_point(ws):
     cfg, xi, b = _feasible_line_instance()
+    if ws:   # a workspace spheroid that holds every line (x in [0, 4.5], y in [-1, 1], z = 0)
+        cfg = replace(cfg, ws_a=3.0, ws_b=0.5, ws_x=2.25)
     s = O.build_system(cfg)
     out, lam, res = O.sf_project(s, torch.tensor(xi), torch.tensor(b), 50)
     assert np.abs(out.numpy() - xi).max() < 1e-12
     assert np.abs(lam.numpy()).max() < 1e-12
     assert res[0, 0].item() < 1e-24
+
+
+def test_workspace_pulls_trajectories_inside():
+    # lines that leave a spheroid workspace are brought inside it (to the R16 tolerance) while
+    # the ends, pinned inside, stay put; the report agrees with a de Casteljau evaluation
+    cfg, xi, b = _feasible_line_instance(n=3)
+    cfg = replace(cfg, ws_a=2.2, ws_b=0.5, ws_x=1.5, ws_y=0.0, vmax=0.0, amax=0.0)
+    xi_bar = xi.copy()
+    xi_bar[:, :, 2, 3:-3] += 0.8     # middle coefficients lifted 0.8 m in z, out of the spheroid (b_w = 0.5)
+    s = O.build_system(cfg)
+    f0 = O.feasibility(s, torch.tensor(xi_bar), torch.tensor(b)).numpy()
+    assert f0[0, 4] > 0.3
+    out, _, _ = O.sf_project(s, torch.tensor(xi_bar), torch.tensor(b), 400)
+    f = O.feasibility(s, out, torch.tensor(b)).numpy()
+    assert f[0, 4] <= 1e-3 and f[0, 3] < 1e-12
+    X, _, _ = curve_on_grid(out.numpy(), cfg.horizon, cfg.t_final)
+    q = ((X[0, :, 0] - 1.5) / 2.2) ** 2 + (X[0, :, 1] / 2.2) ** 2 + (X[0, :, 2] / 0.5) ** 2
+    assert abs(2.2 * (np.sqrt(q.max()) - 1.0) - f[0, 4]) < 1e-12
 
 
 def test_equality_only_limit_is_the_affine_projection():

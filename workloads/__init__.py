@@ -35,6 +35,12 @@ class SwarmConfig:
     rho_coll: float = 1.0
     rho_vel: float = 1.0
     rho_acc: float = 1.0
+    ws_a: float = 0.0        # workspace spheroid semi-axes (x, y and z); 0 switches it off
+    ws_b: float = 0.0
+    rho_ws: float = 1.0
+    ws_x: float = 0.0        # workspace centre
+    ws_y: float = 0.0
+    ws_z: float = 0.0
 
     @property
     def m(self) -> int:
@@ -163,6 +169,15 @@ def swarm16(n_samples: int = 1024, iters: int = 300) -> Workload:
     return Workload("swarm16_3d", [p], iters=iters, precision="fp32")
 
 
+def swarm16ws(n_samples: int = 1024, iters: int = 300) -> Workload:
+    """The 16-robot instance with the workspace constraint on: an origin-centred spheroid of
+    semi-axes 4.8, 4.8, 2.2 m, just large enough to hold the 6x6x2 m box of starts and goals,
+    so that the sampled trajectories that bulge out near its corners are pulled back in."""
+    cfg = replace(cfg_swarm(16), ws_a=4.8, ws_b=2.2)
+    p = box_problem(cfg, n_samples, 0.4, seed=2)
+    return Workload("swarm16ws_3d", [p], iters=iters, precision="fp32")
+
+
 def swarm32(n_samples: int = 4096, iters: int = 300) -> Workload:
     """32 robots in 3D, degree 12, H 120, 4096 samples, 300 iterations."""
     p = box_problem(cfg_swarm(32, degree=12, horizon=120), n_samples, 0.4, seed=4)
@@ -208,6 +223,7 @@ def small3d(n_robots: int = 5, n_samples: int = 6, degree: int = 10, horizon: in
 WORKLOADS = {
     "tiny2d": tiny2d,
     "swarm16": swarm16,
+    "swarm16ws": swarm16ws,
     "ragged": ragged,
     "swarm32": swarm32,
     "diff16": diff16,
