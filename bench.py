@@ -6,9 +6,10 @@ correction terms by default) is timed for exactly --steps calls; the plain FP32 
 beside it on the same inputs, and both are judged at the same final feasibility tolerance.
 Prints one JSON line.
 
-Other workloads (not the headline): --workload swarm32 (32 robots, 4096 samples), ragged (3000
-problems of 8/16/32 robots in one persistent, graph-captured, autotuned launch) and diff16
-(forward with checkpoints + adjoint, gradient evaluations per second).
+Other workloads (not the headline): --workload swarm32 (32 robots, 4096 samples), swarm16ws (the
+16-robot workload with the workspace spheroid rows), ragged (3000 problems of 8/16/32 robots in
+one persistent, graph-captured, autotuned launch) and diff16 (forward with checkpoints +
+adjoint, gradient evaluations per second).
 """
 import argparse
 import hashlib
@@ -38,12 +39,16 @@ def flops_split(cfg):
     contractions (basis evaluation 6nDHm, back-projection to the free coefficients 6nDHm_f, the
     Gram product 4nDm m_f, the QP product 2D(n m_f)^2) and the elementwise VALU work (pair
     projections 15 N_p H, bound balls 24nH, pair scatter 2 N_p H D, multiplier/target update
-    5nDm_f).  Returns (contractions, elementwise)."""
+    5nDm_f; with a workspace, its spheroid projection 12nH: offset 3, scaled norm 5, rsqrt 4
+    counted as in the balls; its back-projection shares the position product).  Returns
+    (contractions, elementwise)."""
     n, D, m, H = cfg.n_robots, cfg.dims, cfg.degree + 1, cfg.horizon
     mf = m - 6
     Np = n * (n - 1) // 2
     dense = 6 * n * D * H * m + 6 * n * D * H * mf + 4 * n * D * m * mf + 2 * D * (n * mf) ** 2
     elem = 15 * Np * H + 24 * n * H + 2 * Np * H * D + 5 * n * D * mf
+    if getattr(cfg, "ws_a", 0.0) > 0:
+        elem += 12 * n * H
     return dense, elem
 
 
@@ -172,12 +177,16 @@ def run_single(args, wl):
     ms, out = form(prec, args.steps, args.warmup)
     n_conv, p99, vmax = judge(sf, out.xi, bv, prec)
     traffic = None if (args.generic or prec == "fp64") else measured_traffic(args.workload, prec)
-    line = base_line(args, f"converged SF projections/sec ({p.cfg.n_robots} robots, 3D); BF16-MFMA vs FP32 at equal residual",
-                     n_conv / (ms / 1e3), ms, DTYPES[prec],
-                     {"workload": wl.name, "samples": S, "robots": p.cfg.n_robots, "dims": p.cfg.dims,
-                      "degree": p.cfg.degree, "horizon": p.cfg.horizon, "iters": K, "precision": prec,
-                      "kernel": "generic" if args.generic else "mfma", "graph": args.graph,
-                      "launch_shape": "autotuned" if args.autotune else "plan default"})
+    ws = getattr(p.cfg, "ws_a", 0.0) > 0
+    config = {"workload": wl.name, "samples": S, "robots": p.cfg.n_robots, "dims": p.cfg.dims,
+              "degree": p.cfg.degree, "horizon": p.cfg.horizon, "iters": K, "precision": prec,
+              "kernel": "generic" if args.generic else "mfma", "graph": args.graph,
+              "launch_shape": "autotuned" if args.autotune else "plan default"}
+    if ws:
+        config["workspace"] = {"semi_axes": [p.cfg.ws_a, p.cfg.ws_a, p.cfg.ws_b],
+                               "centre": [p.cfg.ws_x, p.cfg.ws_y, p.cfg.ws_z]}
+    line = base_line(args, f"converged SF projections/sec ({p.cfg.n_robots} robots, 3D{', workspace' if ws else ''}); "
+                     "BF16-MFMA vs FP32 at equal residual", n_conv / (ms / 1e3), ms, DTYPES[prec], config)
     line.update({"converged_fraction": round(n_conv / S, 6), "violation_p99": p99, "violation_max": vmax,
                  "all_samples_per_s": round(S / (ms / 1e3), 1),
                  "roofline": roofline([(p.cfg, S)], K, ms, prec, traffic)})
@@ -259,7 +268,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="swarm16", choices=["swarm16", "swarm32", "tiny2d", "ragged", "diff16"])
+    ap.add_argument("--workload", default="swarm16",
+                    choices=["swarm16", "swarm16ws", "swarm32", "tiny2d", "ragged", "diff16"])
     ap.add_argument("--precision", default="bf16", choices=["fp64", "fp32", "bf16", "fp16"])
     ap.add_argument("--compare", default="fp32", choices=["fp32", "bf16", "fp16", "none"],
                     help="second form timed beside the headline one")

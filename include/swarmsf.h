@@ -69,20 +69,26 @@ typedef enum {
 #define SF_PERSISTENT 16     /* run a single-shape batch through the persistent work-queue kernel (a
                                 batch of mixed swarm sizes always uses it on the MFMA path) */
 
-/* One problem shape (eqs. poly, inter_robot_con; the velocity and acceleration bounds are
- * origin-centred balls in the polar form of eq. workspace_polar with d in [0, 1]).
+/* One problem shape (eqs. poly, inter_robot_con, workspace_con; the velocity and acceleration
+ * bounds are origin-centred balls in the polar form of eq. workspace_polar with d in [0, 1]).
  *  n_robots >= 2, dims in {2, 3}, degree >= 5 (Bernstein), horizon >= degree + 1,
  *  grid tau_h = h / (horizon - 1), h = 0..horizon-1, over [0, t_final] seconds.
  *  safety_a, safety_b: semi-axes of the centre-to-centre spheroid M_a = diag(a, a, b)
  *  (for spheres of radius r, a = b = 2r).  vmax, amax <= 0 switch that bound off.
  *  rho_*: penalty weights of eq. aug_lag per constraint block (the paper uses one
- *  rho; 1.0 for each block reproduces it). */
+ *  rho; 1.0 for each block reproduces it).
+ *  ws_a, ws_b, ws_x, ws_y, ws_z: the workspace spheroid M_w = diag(a_w, a_w, b_w) about the
+ *  centre p_w of eq. workspace_con (rows F_w of eq. f_e), in the polar form of eq.
+ *  workspace_polar with d in [0, 1]; ws_a <= 0 switches it off (then ws_b, rho_ws and the
+ *  centre are ignored).  In 2D only ws_a, ws_x and ws_y count. */
 typedef struct {
   int32_t n_robots, dims, degree, horizon;
   double t_final;
   double safety_a, safety_b;
   double vmax, amax;
   double rho_coll, rho_vel, rho_acc;
+  double ws_a, ws_b, rho_ws;
+  double ws_x, ws_y, ws_z;
 } sf_config;
 
 /* A batch of problems (host arrays of length n_problems).  cfg_slot indexes the
@@ -126,7 +132,8 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision,
  * and the ckpt it wrote) through the unrolled iterations, eq. (NN_loss) style
  * training of the initialisation.  Given cotangents of xi_out, lam_out and of
  * resid_out[:, 0] (each may be NULL = zero) it writes the gradients with respect to
- * xi0, lam0 and xi_bar (each may be NULL = not wanted).  g_resid is [S]. */
+ * xi0, lam0 and xi_bar (each may be NULL = not wanted).  g_resid is [S].  A batch with a
+ * workspace constraint (ws_a > 0) returns SF_EUNSUPPORTED. */
 sf_status sf_project_backward(sf_handle h, const sf_batch* batch, int32_t precision,
                               const void* xi_bar, const void* bvals, int32_t iters,
                               const void* ckpt, int32_t ckpt_every,
@@ -135,8 +142,9 @@ sf_status sf_project_backward(sf_handle h, const sf_batch* batch, int32_t precis
 
 /* Constraint violations of coefficient arrays, computed in FP64 on the device at the
  * grid times.  xi is [S, n, D, m] (double for SF_FP64, else float); viol_out is
- * double [S, 4] = (a * (1 - min ||M_a^{-1}(p_i - p_j)||), max ||v|| - vmax,
- * max ||acc|| - amax, max |A xi - b|); positive means violated. */
+ * double [S, 5] = (a * (1 - min ||M_a^{-1}(p_i - p_j)||), max ||v|| - vmax,
+ * max ||acc|| - amax, max |A xi - b|, a_w * (max ||M_w^{-1}(p_i - p_w)|| - 1), the last 0
+ * without a workspace); positive means violated. */
 sf_status sf_feasibility(sf_handle h, const sf_batch* batch, int32_t precision,
                          const void* xi, const void* bvals, void* viol_out, void* stream);
 

@@ -22,7 +22,9 @@ class SfConfig(ctypes.Structure):
     _fields_ = [("n_robots", c_int32), ("dims", c_int32), ("degree", c_int32), ("horizon", c_int32),
                 ("t_final", c_double), ("safety_a", c_double), ("safety_b", c_double),
                 ("vmax", c_double), ("amax", c_double),
-                ("rho_coll", c_double), ("rho_vel", c_double), ("rho_acc", c_double)]
+                ("rho_coll", c_double), ("rho_vel", c_double), ("rho_acc", c_double),
+                ("ws_a", c_double), ("ws_b", c_double), ("rho_ws", c_double),
+                ("ws_x", c_double), ("ws_y", c_double), ("ws_z", c_double)]
 
 
 class SfBatch(ctypes.Structure):
@@ -77,4 +79,7 @@ def make_config(c) -> SfConfig:
     return SfConfig(int(c.n_robots), int(c.dims), int(c.degree), int(c.horizon), float(c.t_final),
                     float(c.safety_a), float(c.safety_b), float(c.vmax), float(c.amax),
                     float(getattr(c, "rho_coll", 1.0)), float(getattr(c, "rho_vel", 1.0)),
-                    float(getattr(c, "rho_acc", 1.0)))
+                    float(getattr(c, "rho_acc", 1.0)),
+                    float(getattr(c, "ws_a", 0.0)), float(getattr(c, "ws_b", 0.0)),
+                    float(getattr(c, "rho_ws", 1.0)), float(getattr(c, "ws_x", 0.0)),
+                    float(getattr(c, "ws_y", 0.0)), float(getattr(c, "ws_z", 0.0)))

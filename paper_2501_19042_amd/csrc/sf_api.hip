@@ -97,6 +97,10 @@ sf_status check_config(const sf_config& c) {
   if (!(c.rho_coll > 0)) return fail(SF_EINVAL, "rho_coll must be > 0");
   if (c.vmax > 0 && !(c.rho_vel > 0)) return fail(SF_EINVAL, "rho_vel must be > 0 when vmax > 0");
   if (c.amax > 0 && !(c.rho_acc > 0)) return fail(SF_EINVAL, "rho_acc must be > 0 when amax > 0");
+  if (c.ws_a > 0 && c.dims == 3 && !(c.ws_b > 0)) return fail(SF_EINVAL, "ws_b must be > 0 when ws_a > 0");
+  if (c.ws_a > 0 && !(c.rho_ws > 0)) return fail(SF_EINVAL, "rho_ws must be > 0 when ws_a > 0");
+  if (c.ws_a > 0 && !(std::isfinite(c.ws_x) && std::isfinite(c.ws_y) && std::isfinite(c.ws_z)))
+    return fail(SF_EINVAL, "workspace centre must be finite");
   if (c.n_robots > 64) return fail(SF_EUNSUPPORTED, "n_robots > 64 is not supported");
   if (c.degree > 30 || c.horizon > 4096) return fail(SF_EUNSUPPORTED, "degree > 30 or horizon > 4096");
   return SF_OK;
@@ -107,7 +111,7 @@ sf_status build_cfg(const sf_config& c, HostCfg& out) {
   if (st != SF_OK) return st;
   const int N = c.degree, m = N + 1, mf = m - sf::kNFix, H = c.horizon, n = c.n_robots;
   const double T = c.t_final;
-  const bool vel = c.vmax > 0, acc = c.amax > 0;
+  const bool vel = c.vmax > 0, acc = c.amax > 0, ws = c.ws_a > 0;
   std::vector<double> P(H * m), Pd(H * m), Pdd(H * m);
   for (int h = 0; h < H; ++h) {
     const double tau = (double)h / (H - 1);
@@ -138,7 +142,8 @@ sf_status build_cfg(const sf_config& c, HostCfg& out) {
         ra += Pdd[h * m + k] * Pdd[h * m + l];
       }
       G[k * m + l] = g;
-      Rm[k * m + l] = (vel ? c.rho_vel * rv : 0.0) + (acc ? c.rho_acc * ra : 0.0);
+      // per-robot rows: velocity and acceleration bounds, and the workspace (F_w of eq. f_e)
+      Rm[k * m + l] = (vel ? c.rho_vel * rv : 0.0) + (acc ? c.rho_acc * ra : 0.0) + (ws ? c.rho_ws * g : 0.0);
     }
   // Free-coefficient blocks of the KKT inverse: Z^T Q Z = J (x) (I + Rff) + (I - J) (x) (I + n rho Gff + Rff)
   std::vector<double> X0(mf * mf), X1(mf * mf), X01(mf * mf), Gfx(mf * 6), Rfx(mf * 6);
@@ -166,6 +171,18 @@ sf_status build_cfg(const sf_config& c, HostCfg& out) {
   d.vmax = vel ? c.vmax : 0.0; d.amax = acc ? c.amax : 0.0;
   d.rho_c = c.rho_coll; d.rho_v = vel ? c.rho_vel : 0.0; d.rho_a = acc ? c.rho_acc : 0.0;
   d.n_rho_c = n * c.rho_coll;
+  d.ws_on = ws;
+  if (ws) {
+    const double wb = c.dims == 3 ? c.ws_b : c.ws_a;
+    d.ws_a = c.ws_a;
+    d.ws_ia2 = 1.0 / (c.ws_a * c.ws_a);
+    d.ws_ib2 = 1.0 / (wb * wb);
+    d.ws_c[0] = c.ws_x; d.ws_c[1] = c.ws_y; d.ws_c[2] = c.dims == 3 ? c.ws_z : 0.0;
+    d.rho_w = c.rho_ws;
+    d.ws_scale = c.rho_ws / c.rho_coll;
+    const double wf[6] = {d.ws_c[0], d.ws_c[1], d.ws_c[2], d.ws_ia2, d.ws_ib2, d.ws_scale};
+    for (int q = 0; q < 6; ++q) d.ws_f[q] = (float)wf[q];
+  }
   d.lip_v = d.lip_a = 0.0;
   for (int h = 0; h < H; ++h) {
     double sv = 0.0, sa = 0.0;
@@ -378,6 +395,7 @@ std::string tune_signature(sf_handle h, const Plan* p, int precision) {
   for (int32_t s : p->slots_used) {
     const sf::DevCfg& c = h->cfgs[s].dev;
     mix(c.n); mix(c.m); mix(c.H); mix(c.D);
+    if (c.ws_on) mix(0x7773);   // workspace instances are other kernels
   }
   hipDeviceProp_t prop;
   std::string arch = "unknown";
@@ -430,6 +448,7 @@ sf_status autotune(sf_handle h, const Plan* p, sf::FastPlan& fp, const sf::Launc
   // candidates: waves per workgroup x (persistent only) workgroups in flight
   std::vector<std::pair<int, int>> cand;
   for (int W : {2, 3, 4}) {
+    if (fp.ws && W > 3) continue;   // the workspace instances have 2 or 3 waves per workgroup
     if (!fp.batched) {
       cand.push_back({W, 0});
       continue;
@@ -728,6 +747,7 @@ sf_status sf_project_backward(sf_handle h, const sf_batch* batch, int32_t precis
   int64_t max_ndm = 0;
   for (int32_t s : p->slots_used) {
     const sf::DevCfg& c = h->cfgs[s].dev;
+    if (c.ws_on) return fail(SF_EUNSUPPORTED, "the adjoint does not cover the workspace rows");
     max_ndm = std::max<int64_t>(max_ndm, (int64_t)c.n * c.D * c.m);
   }
   sf::AdjointArgs a{};

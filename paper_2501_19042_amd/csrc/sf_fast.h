@@ -34,6 +34,8 @@ struct FastPlan {
   int ncu = 0;
   int tuned_grid[4] = {0, 0, 0, 0};     // autotuned persistent workgroups per precision (0 = not tuned)
   int tuned_w[4] = {0, 0, 0, 0};        // autotuned waves per workgroup per precision (0 = not tuned)
+  bool ws = false;                      // some config has a workspace: kernels with its rows, and
+                                        // 2 or 3 waves per workgroup
 };
 
 sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<DevProblem>& probs,

@@ -221,8 +221,9 @@ struct FastArgs {
   int64_t ckpt_stride;
 };
 
-// The whole solve of one work item (its samples) by one workgroup.
-template <int R, int KS, int W, int MP>
+// The whole solve of one work item (its samples) by one workgroup.  WS: the instance carries the
+// workspace rows (evaluated for the configs that have them).
+template <int R, int KS, int W, int MP, int WS>
 __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem) {
   const DevCfg* __restrict__ cfgs = A.cfgs;
   const float* __restrict__ tab = A.tab;
@@ -273,6 +274,9 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
     const float* Gfx = tab + c.off_Gfx;
     const float* Rfx = tab + c.off_Rfx;
     const float ia2 = (float)c.inv_a2, ib2 = (float)c.inv_b2, sb = (float)c.b;
+    // workspace spheroid (eq. workspace_polar): centre, 1/a_w^2, 1/b_w^2, rho_w / rho_c
+    const float wcx = c.ws_f[0], wcy = c.ws_f[1], wcz = c.ws_f[2];
+    const float wia2 = c.ws_f[3], wib2 = c.ws_f[4], wsc = c.ws_f[5];
     const float vmax = (float)c.vmax, amax = (float)c.amax;
     const float n_rho_c = (float)c.n_rho_c, inv_n = 1.0f / (float)n;
     const float Lv = (float)c.lip_v, La = (float)c.lip_a;
@@ -570,6 +574,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             }
             pb = a32c[((nx * 3) * 2 + 1) * 64 + lane];
           }
+          bool ws_nz = false;   // some workspace residual of the tile is nonzero (wave-uniform)
           // ---- S1 positions -> LDS, per-robot boxes over the tile in registers ----
           {
             f4 Y[R][3];
@@ -595,6 +600,33 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                 float* bq = bb + (16 * rr + col) * kBoxRow;
                 *reinterpret_cast<f4*>(bq) = f4{lo[0], lo[1], lo[2], 0.0f};
                 *reinterpret_cast<f4*>(bq + 4) = f4{hi[0], hi[1], hi[2], 0.0f};
+              }
+            }
+            // workspace rows (F_w of eq. f_e) on the same positions: residual (p - p_w) max(0,
+            // 1 - 1/||M_w^{-1} (p - p_w)||), scaled by rho_w / rho_c so that it joins the collision
+            // residuals in the accumulator (zero until now) and their S4 product
+            if (WS && c.ws_on) {
+              bool wnz = false;
+#pragma unroll
+              for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  const float qx = Y[rr][0][r] - wcx, qy = Y[rr][1][r] - wcy, qz = Y[rr][2][r] - wcz;
+                  const float s2 = (qx * qx + qy * qy) * wia2 + qz * qz * wib2;
+                  // (s2 > 1 is a normal number, so the bare hardware rsqrt serves)
+                  const float f = (16 * rr + col < n && s2 > 1.0f) ? wsc * (1.0f - __builtin_amdgcn_rsqf(s2)) : 0.0f;
+                  Y[rr][0][r] = f * qx;
+                  Y[rr][1][r] = f * qy;
+                  Y[rr][2][r] = f * qz;
+                  wnz |= f != 0.0f;
+                }
+              if (ballot(wnz) != 0) {
+                ws_nz = true;
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+                  for (int d = 0; d < 3; ++d)
+                    *reinterpret_cast<f4*>(Ct + tile_at(d * NR + 16 * rr + col, 4 * grp)) = Y[rr][d];
               }
             }
           }
@@ -701,7 +733,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
               }
             }
           }
-          if (ballot(nzc) != 0) {
+          if (ws_nz || ballot(nzc) != 0) {
             wave_sync();
             const float b4[4] = {cb.x, cb.y, cb.z, cb.w};
 #pragma unroll
@@ -970,6 +1002,24 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
 #pragma unroll
                   for (int d = 0; d < 3; ++d)
                     *reinterpret_cast<f4*>(Ct + tile_at(d * NR + 16 * rr + col, 4 * grp)) = Yn[rr][d];
+                if (WS && c.ws_on) {
+                  // workspace rows: r_p = p_new - e(p_prev), e = p - (p - p_w) max(0, 1 - 1/||s||)
+#pragma unroll
+                  for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                      const float qx = Y[rr][0][r] - wcx, qy = Y[rr][1][r] - wcy, qz = Y[rr][2][r] - wcz;
+                      const float s2 = (qx * qx + qy * qy) * wia2 + qz * qz * wib2;
+                      const float f = s2 > 1.0f ? 1.0f - rsqrtf(s2) : 0.0f;
+                      const float px = Yn[rr][0][r] - (Y[rr][0][r] - f * qx);
+                      const float py = Yn[rr][1][r] - (Y[rr][1][r] - f * qy);
+                      const float pz = Yn[rr][2][r] - (Y[rr][2][r] - f * qz);
+                      const bool real = 4 * grp + r < nt && 16 * rr + col < n;   // grid times, robots
+                      const float nrm = real ? px * px + py * py + pz * pz : 0.0f;
+                      ss += nrm;
+                      mx = fmaxf(mx, nrm);
+                    }
+                }
                 continue;
               }
               // bound balls: r_p = v_new - e(v_prev)
@@ -1036,17 +1086,17 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
 }
 
 // One workgroup per work item (grid-stride), single shape class.
-template <int R, int KS, int W, int MP, int WPE>
+template <int R, int KS, int W, int MP, int WPE, int WS>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 fast_project_kernel(FastArgs A) {
   extern __shared__ __align__(16) float smem[];
-  for (int it = blockIdx.x; it < A.n_items; it += gridDim.x) fast_item<R, KS, W, MP>(A, it, smem);
+  for (int it = blockIdx.x; it < A.n_items; it += gridDim.x) fast_item<R, KS, W, MP, WS>(A, it, smem);
 }
 
 // Persistent kernel over the work items of one robot-tile class (R tiles of 16 robots) of a
 // ragged batch: workgroups pull items (sorted by decreasing cost on the host) from an atomic
 // queue until it is empty.  Every wave reaches the exit once the queue is drained.
-template <int R, int KS, int W, int MP, int WPE>
+template <int R, int KS, int W, int MP, int WPE, int WS>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 fast_batched_kernel(FastArgs A, int* __restrict__ queue) {
   extern __shared__ __align__(16) float smem[];
@@ -1057,7 +1107,7 @@ fast_batched_kernel(FastArgs A, int* __restrict__ queue) {
     const int it = __builtin_amdgcn_readfirstlane(next);
     __syncthreads();
     if (it >= A.n_items) break;
-    fast_item<R, KS, W, MP>(A, it, smem);
+    fast_item<R, KS, W, MP, WS>(A, it, smem);
   }
 }
 
@@ -1084,9 +1134,9 @@ FastArgs make_fast_args(const LaunchArgs& a, const float* tab32, const uint4* a1
   return f;
 }
 
-template <int R, int KS, int W, int MP>
+template <int R, int KS, int W, int MP, int WS>
 hipError_t launch_instance(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16) {
-  auto kern = fast_project_kernel<R, KS, W, MP, waves_per_simd(R, MP)>;
+  auto kern = fast_project_kernel<R, KS, W, MP, waves_per_simd(R, MP), WS>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes[W - 2][MP]);
   if (e != hipSuccess) return e;
@@ -1200,6 +1250,7 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
     const DevCfg& c = cfgs[p.cfg];
     if (!cfg_supported(c)) return SF_OK;                 // generic path
     if (p.cfg != probs[0].cfg) mixed = true;
+    if (c.ws_on) out.ws = true;
     maxKS = std::max(maxKS, (c.m + 3) / 4);
     maxNT = std::max(maxNT, (c.H + 15) / 16);
     for (int wi = 0; wi < 3; ++wi)
@@ -1284,9 +1335,9 @@ void fast_plan_free(FastPlan& p) {
 
 namespace {
 
-template <int R, int KS, int W, int MP>
+template <int R, int KS, int W, int MP, int WS>
 hipError_t launch_class(const FastClass& C, const FastArgs& f, int grid, int* queue, hipStream_t stream) {
-  auto kern = fast_batched_kernel<R, KS, W, MP, waves_per_simd(R, MP)>;
+  auto kern = fast_batched_kernel<R, KS, W, MP, waves_per_simd(R, MP), WS>;
   const size_t lds = C.lds_bytes[W - 2][MP];
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
@@ -1296,7 +1347,7 @@ hipError_t launch_class(const FastClass& C, const FastArgs& f, int grid, int* qu
 }
 
 // grid > 0: workgroups per class launch (at most its work items); 0: each class's default.
-template <int KS, int W, int MP>
+template <int KS, int W, int MP, int WS>
 hipError_t launch_batched(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16, int grid) {
   hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, a.stream, p.d_queue, p.n_cls);
   for (int ci = 0; ci < p.n_cls; ++ci) {
@@ -1305,8 +1356,8 @@ hipError_t launch_batched(const FastPlan& p, const LaunchArgs& a, const float* t
     f.items = p.d_items_sorted + C.offset;
     f.n_items = C.n_items;
     const int g = std::max(1, std::min(C.n_items, grid > 0 ? grid : C.grid));
-    const hipError_t e = C.R == 1 ? launch_class<1, KS, W, MP>(C, f, g, p.d_queue + ci, a.stream)
-                                  : launch_class<2, KS, W, MP>(C, f, g, p.d_queue + ci, a.stream);
+    const hipError_t e = C.R == 1 ? launch_class<1, KS, W, MP, WS>(C, f, g, p.d_queue + ci, a.stream)
+                                  : launch_class<2, KS, W, MP, WS>(C, f, g, p.d_queue + ci, a.stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1315,17 +1366,24 @@ hipError_t launch_batched(const FastPlan& p, const LaunchArgs& a, const float* t
 template <int MP>
 hipError_t launch_batched_mp(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16, int grid,
                              int W) {
-  const int key = p.KS * 10 + W;
+  const int key = p.KS * 10 + W + (p.ws ? 1000 : 0);
   switch (key) {
-    case 22: return launch_batched<2, 2, MP>(p, a, tab32, a16, grid);
-    case 23: return launch_batched<2, 3, MP>(p, a, tab32, a16, grid);
-    case 24: return launch_batched<2, 4, MP>(p, a, tab32, a16, grid);
-    case 32: return launch_batched<3, 2, MP>(p, a, tab32, a16, grid);
-    case 33: return launch_batched<3, 3, MP>(p, a, tab32, a16, grid);
-    case 34: return launch_batched<3, 4, MP>(p, a, tab32, a16, grid);
-    case 42: return launch_batched<4, 2, MP>(p, a, tab32, a16, grid);
-    case 43: return launch_batched<4, 3, MP>(p, a, tab32, a16, grid);
-    case 44: return launch_batched<4, 4, MP>(p, a, tab32, a16, grid);
+    case 22: return launch_batched<2, 2, MP, 0>(p, a, tab32, a16, grid);
+    case 23: return launch_batched<2, 3, MP, 0>(p, a, tab32, a16, grid);
+    case 24: return launch_batched<2, 4, MP, 0>(p, a, tab32, a16, grid);
+    case 32: return launch_batched<3, 2, MP, 0>(p, a, tab32, a16, grid);
+    case 33: return launch_batched<3, 3, MP, 0>(p, a, tab32, a16, grid);
+    case 34: return launch_batched<3, 4, MP, 0>(p, a, tab32, a16, grid);
+    case 42: return launch_batched<4, 2, MP, 0>(p, a, tab32, a16, grid);
+    case 43: return launch_batched<4, 3, MP, 0>(p, a, tab32, a16, grid);
+    case 44: return launch_batched<4, 4, MP, 0>(p, a, tab32, a16, grid);
+    // with the workspace rows: 2 or 3 waves per workgroup
+    case 1022: return launch_batched<2, 2, MP, 1>(p, a, tab32, a16, grid);
+    case 1023: return launch_batched<2, 3, MP, 1>(p, a, tab32, a16, grid);
+    case 1032: return launch_batched<3, 2, MP, 1>(p, a, tab32, a16, grid);
+    case 1033: return launch_batched<3, 3, MP, 1>(p, a, tab32, a16, grid);
+    case 1042: return launch_batched<4, 2, MP, 1>(p, a, tab32, a16, grid);
+    case 1043: return launch_batched<4, 3, MP, 1>(p, a, tab32, a16, grid);
     default:
       g_fast_err = "no persistent kernel instance for this shape";
       return hipErrorNotSupported;
@@ -1349,23 +1407,34 @@ hipError_t fast_launch_batched(const FastPlan& p, const LaunchArgs& a, const flo
 
 template <int MP>
 hipError_t launch_mp(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16, int W) {
-  const int key = p.R * 100 + p.KS * 10 + W;
+  const int key = p.R * 100 + p.KS * 10 + W + (p.ws ? 1000 : 0);
   switch (key) {
-    case 122: return launch_instance<1, 2, 2, MP>(p, a, tab32, a16);
-    case 123: return launch_instance<1, 2, 3, MP>(p, a, tab32, a16);
-    case 124: return launch_instance<1, 2, 4, MP>(p, a, tab32, a16);
-    case 132: return launch_instance<1, 3, 2, MP>(p, a, tab32, a16);
-    case 133: return launch_instance<1, 3, 3, MP>(p, a, tab32, a16);
-    case 134: return launch_instance<1, 3, 4, MP>(p, a, tab32, a16);
-    case 142: return launch_instance<1, 4, 2, MP>(p, a, tab32, a16);
-    case 143: return launch_instance<1, 4, 3, MP>(p, a, tab32, a16);
-    case 144: return launch_instance<1, 4, 4, MP>(p, a, tab32, a16);
-    case 232: return launch_instance<2, 3, 2, MP>(p, a, tab32, a16);
-    case 233: return launch_instance<2, 3, 3, MP>(p, a, tab32, a16);
-    case 234: return launch_instance<2, 3, 4, MP>(p, a, tab32, a16);
-    case 242: return launch_instance<2, 4, 2, MP>(p, a, tab32, a16);
-    case 243: return launch_instance<2, 4, 3, MP>(p, a, tab32, a16);
-    case 244: return launch_instance<2, 4, 4, MP>(p, a, tab32, a16);
+    case 122: return launch_instance<1, 2, 2, MP, 0>(p, a, tab32, a16);
+    case 123: return launch_instance<1, 2, 3, MP, 0>(p, a, tab32, a16);
+    case 124: return launch_instance<1, 2, 4, MP, 0>(p, a, tab32, a16);
+    case 132: return launch_instance<1, 3, 2, MP, 0>(p, a, tab32, a16);
+    case 133: return launch_instance<1, 3, 3, MP, 0>(p, a, tab32, a16);
+    case 134: return launch_instance<1, 3, 4, MP, 0>(p, a, tab32, a16);
+    case 142: return launch_instance<1, 4, 2, MP, 0>(p, a, tab32, a16);
+    case 143: return launch_instance<1, 4, 3, MP, 0>(p, a, tab32, a16);
+    case 144: return launch_instance<1, 4, 4, MP, 0>(p, a, tab32, a16);
+    case 232: return launch_instance<2, 3, 2, MP, 0>(p, a, tab32, a16);
+    case 233: return launch_instance<2, 3, 3, MP, 0>(p, a, tab32, a16);
+    case 234: return launch_instance<2, 3, 4, MP, 0>(p, a, tab32, a16);
+    case 242: return launch_instance<2, 4, 2, MP, 0>(p, a, tab32, a16);
+    case 243: return launch_instance<2, 4, 3, MP, 0>(p, a, tab32, a16);
+    case 244: return launch_instance<2, 4, 4, MP, 0>(p, a, tab32, a16);
+    // with the workspace rows: 2 or 3 waves per workgroup
+    case 1122: return launch_instance<1, 2, 2, MP, 1>(p, a, tab32, a16);
+    case 1123: return launch_instance<1, 2, 3, MP, 1>(p, a, tab32, a16);
+    case 1132: return launch_instance<1, 3, 2, MP, 1>(p, a, tab32, a16);
+    case 1133: return launch_instance<1, 3, 3, MP, 1>(p, a, tab32, a16);
+    case 1142: return launch_instance<1, 4, 2, MP, 1>(p, a, tab32, a16);
+    case 1143: return launch_instance<1, 4, 3, MP, 1>(p, a, tab32, a16);
+    case 1232: return launch_instance<2, 3, 2, MP, 1>(p, a, tab32, a16);
+    case 1233: return launch_instance<2, 3, 3, MP, 1>(p, a, tab32, a16);
+    case 1242: return launch_instance<2, 4, 2, MP, 1>(p, a, tab32, a16);
+    case 1243: return launch_instance<2, 4, 3, MP, 1>(p, a, tab32, a16);
     default:
       g_fast_err = "no kernel instance for this shape";
       return hipErrorNotSupported;
@@ -1373,7 +1442,8 @@ hipError_t launch_mp(const FastPlan& p, const LaunchArgs& a, const float* tab32,
 }
 
 hipError_t fast_launch(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16, int precision) {
-  const int W = p.tuned_w[precision & 3] > 0 ? p.tuned_w[precision & 3] : p.Wp[precision & 3];
+  int W = p.tuned_w[precision & 3] > 0 ? p.tuned_w[precision & 3] : p.Wp[precision & 3];
+  if (p.ws && W > 3) W = 3;   // the workspace instances have 2 or 3 waves per workgroup
   if (p.batched) {
     const int g = p.tuned_grid[precision & 3];
     return fast_launch_batched(p, a, tab32, a16, precision, g, W);

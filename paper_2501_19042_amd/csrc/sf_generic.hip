@@ -89,7 +89,7 @@ generic_project_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ ta
 // ---------------------------------------------------------------------------------
 
 __host__ __device__ inline size_t feas_elems(const DevCfg& c, int TT) {
-  return (size_t)c.n * c.D * c.m + (size_t)3 * c.n * c.D * TT + 4 * kBlock;
+  return (size_t)c.n * c.D * c.m + (size_t)3 * c.n * c.D * TT + 5 * kBlock;
 }
 
 template <typename Tin>
@@ -114,7 +114,7 @@ feasibility_kernel(const DevCfg* __restrict__ cfgs, const double* __restrict__ t
       const int64_t sidx = pr.sample_base + sl;
       for (int q = threadIdx.x; q < nDm; q += blockDim.x) x[q] = (double)xi[coef + q];
       __syncthreads();
-      double smin = DBL_MAX, vmx = 0.0, amx = 0.0, bmx = 0.0;
+      double smin = DBL_MAX, vmx = 0.0, amx = 0.0, bmx = 0.0, wmx = 0.0;
       for (int q = threadIdx.x; q < nD * kNFix; q += blockDim.x) {
         const int row = q / kNFix, r = q - row * kNFix;
         const int bsel = r % 3;
@@ -154,24 +154,34 @@ feasibility_kernel(const DevCfg* __restrict__ cfgs, const double* __restrict__ t
           }
           vmx = fmax(vmx, v2);
           amx = fmax(amx, a2);
+          if (c.ws_on) {   // ||M_w^{-1} (p_i - p_w)||^2 of eq. workspace_con
+            double w2 = 0.0;
+            for (int d = 0; d < D; ++d) {
+              const double r = Y[(i * D + d) * TT + tt] - c.ws_c[d];
+              w2 += r * r * (d == 2 ? c.ws_ib2 : c.ws_ia2);
+            }
+            wmx = fmax(wmx, w2);
+          }
         }
         __syncthreads();
       }
       const int t = threadIdx.x;
       red[t] = smin; red[kBlock + t] = vmx; red[2 * kBlock + t] = amx; red[3 * kBlock + t] = bmx;
+      red[4 * kBlock + t] = wmx;
       __syncthreads();
       for (int s = kBlock / 2; s > 0; s >>= 1) {
         if (t < s) {
           red[t] = fmin(red[t], red[t + s]);
-          for (int r = 1; r < 4; ++r) red[r * kBlock + t] = fmax(red[r * kBlock + t], red[r * kBlock + t + s]);
+          for (int r = 1; r < 5; ++r) red[r * kBlock + t] = fmax(red[r * kBlock + t], red[r * kBlock + t + s]);
         }
         __syncthreads();
       }
       if (t == 0) {
-        viol[sidx * 4 + 0] = c.a * (1.0 - sqrt(red[0]));
-        viol[sidx * 4 + 1] = c.vel_on ? sqrt(red[kBlock]) - c.vmax : -DBL_MAX;
-        viol[sidx * 4 + 2] = c.acc_on ? sqrt(red[2 * kBlock]) - c.amax : -DBL_MAX;
-        viol[sidx * 4 + 3] = red[3 * kBlock];
+        viol[sidx * 5 + 0] = c.a * (1.0 - sqrt(red[0]));
+        viol[sidx * 5 + 1] = c.vel_on ? sqrt(red[kBlock]) - c.vmax : -DBL_MAX;
+        viol[sidx * 5 + 2] = c.acc_on ? sqrt(red[2 * kBlock]) - c.amax : -DBL_MAX;
+        viol[sidx * 5 + 3] = red[3 * kBlock];
+        viol[sidx * 5 + 4] = c.ws_on ? c.ws_a * (sqrt(red[4 * kBlock]) - 1.0) : 0.0;
       }
       __syncthreads();
     }

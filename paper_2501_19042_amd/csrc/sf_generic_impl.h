@@ -88,6 +88,21 @@ __device__ __forceinline__ void ball_resid(const T* v, int D, T lim, T* R) {
   for (int d = 0; d < D; ++d) R[d] = f * v[d];
 }
 
+// Residual of the workspace projection (eq. workspace_polar, d in [0, 1]) of a robot position p:
+// with s = M_w^{-1} (p - p_w) the target is p_w + (p - p_w) min(1, 1/||s||), so the residual is
+// (p - p_w) max(0, 1 - 1/||s||).
+template <typename T>
+__device__ __forceinline__ void ws_resid(const T* p, int D, const T* wc, T ia2, T ib2, T* R) {
+  T q[3] = {T(0), T(0), T(0)};
+  T ss = T(0);
+  for (int d = 0; d < D; ++d) {
+    q[d] = p[d] - wc[d];
+    ss += q[d] * q[d] * (d == 2 ? ib2 : ia2);
+  }
+  const T f = (ss > T(1)) ? T(1) - rsq<T>(ss) : T(0);
+  for (int d = 0; d < D; ++d) R[d] = f * q[d];
+}
+
 // dst[b][i][d][tt] = sum_k basis[b][t0+tt][k] * src[i][d][k] for the enabled bases.
 template <typename T>
 __device__ void eval_tile(const DevCfg& c, const T* __restrict__ basis, const T* src, T* dst,
@@ -165,6 +180,18 @@ __device__ void residual_pass(const DevCfg& c, const T* __restrict__ basis, cons
         ss += nrm;
         mx = max(mx, nrm);
       }
+      if (c.ws_on) {   // workspace rows: positions against the previous iterate's targets
+        const T wc[3] = {T(c.ws_c[0]), T(c.ws_c[1]), T(c.ws_c[2])};
+        T v[3], R[3], nrm = T(0);
+        for (int d = 0; d < D; ++d) v[d] = L.Y[(i * D + d) * TT + tt];
+        ws_resid<T>(v, D, wc, T(c.ws_ia2), T(c.ws_ib2), R);
+        for (int d = 0; d < D; ++d) {
+          const T rp = L.Rb[(i * D + d) * TT + tt] - (v[d] - R[d]);
+          nrm += rp * rp;
+        }
+        ss += nrm;
+        mx = max(mx, nrm);
+      }
     }
     __syncthreads();
   }
@@ -180,6 +207,7 @@ struct Ctx {
   DevCfg c;
   const T *basis, *X1, *X01, *Bmap, *Gfx, *Rfx;
   T ia2, ib2, a, b, vmax, amax, rho_c, rho_v, rho_a, n_rho_c, inv_n;
+  T ws_ia2, ws_ib2, ws_scale, wc[3];
   int n, D, m, mf, nD, nDm, nDf, nD6;
 };
 
@@ -193,6 +221,8 @@ __device__ Ctx<T> make_ctx(const DevCfg& c, const T* tab) {
   x.vmax = T(c.vmax); x.amax = T(c.amax);
   x.rho_c = T(c.rho_c); x.rho_v = T(c.rho_v); x.rho_a = T(c.rho_a); x.n_rho_c = T(c.n_rho_c);
   x.inv_n = T(1) / T(c.n);
+  x.ws_ia2 = T(c.ws_ia2); x.ws_ib2 = T(c.ws_ib2); x.ws_scale = T(c.ws_scale);
+  for (int d = 0; d < 3; ++d) x.wc[d] = T(c.ws_c[d]);
   x.n = c.n; x.D = c.D; x.m = c.m; x.mf = c.mf; x.nD = c.n * c.D;
   x.nDm = x.nD * c.m; x.nDf = x.nD * c.mf; x.nD6 = x.nD * kNFix;
   return x;
@@ -265,6 +295,11 @@ __device__ void iteration(const Ctx<T>& x, const Lds<T>& L, int TT, int k) {
         for (int d = 0; d < D; ++d) r[d] = xi_[d] - L.Y[(j * D + d) * TT + tt];
         coll_resid<T>(r, D, x.ia2, x.ib2, x.a, x.b, i < j, R);
         for (int d = 0; d < D; ++d) C[d] += R[d];
+      }
+      if (c.ws_on) {   // workspace rows share the position basis; weight rho_w = rho_c ws_scale
+        T R[3];
+        ws_resid<T>(xi_, D, x.wc, x.ws_ia2, x.ws_ib2, R);
+        for (int d = 0; d < D; ++d) C[d] = fma(x.ws_scale, R[d], C[d]);
       }
       for (int d = 0; d < D; ++d) L.Rb[(i * D + d) * TT + tt] = C[d];
       if (c.vel_on) {

@@ -17,13 +17,21 @@ constexpr int kNFix = 6;             // coefficients pinned by the boundary rows
 //   Bmap  [6][6]      pinned coefficients (c0, c1, c2, c_{N-2}, c_{N-1}, c_N) from
 //                     (p0, v0, a0, pH, vH, aH)
 //   Gfx   [mf][6]     G = P^T P, free rows x pinned columns
-//   Rfx   [mf][6]     Rm = rho_v Pd^T Pd + rho_a Pdd^T Pdd, free rows x pinned columns
+//   Rfx   [mf][6]     Rm = rho_v Pd^T Pd + rho_a Pdd^T Pdd (+ rho_w P^T P with a workspace),
+//                     free rows x pinned columns
 struct DevCfg {
   int32_t n, D, m, mf, H, Np;
   int32_t vel_on, acc_on;
   double a, b, inv_a2, inv_b2, vmax, amax;
   double rho_c, rho_v, rho_a, n_rho_c;
   double lip_v, lip_a;    // max_t sum_k |Pd[t][k]|, max_t sum_k |Pdd[t][k]|: drift bounds of v, acc
+  int32_t ws_on, pad_;
+  double ws_a, ws_ia2, ws_ib2;  // workspace semi-axis a_w, 1/a_w^2, 1/b_w^2 (eq. workspace_polar)
+  double ws_c[3];               // workspace centre p_w
+  double rho_w, ws_scale;       // rho of the workspace rows, and rho_w / rho_c
+  float ws_f[6];                // fp32 copies (centre, 1/a_w^2, 1/b_w^2, rho_w / rho_c) for the
+                                // MFMA kernels, read as scalars without a conversion
+  float pad2_[2];
   double skin;            // pair-list margin of the MFMA broad phase, as a fraction of the safety
                           // semi-axes (a for x, y; b for z)
   int64_t off_basis, off_X1, off_X01, off_Bmap, off_Gfx, off_Rfx;

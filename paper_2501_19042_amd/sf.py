@@ -149,7 +149,7 @@ class SafetyFilter:
         S, coef, bnd = self.sizes(batch)
         self._check(xi, "xi", dtype, coef)
         self._check(bvals, "bvals", dtype, bnd)
-        viol = torch.empty((S, 4), dtype=torch.float64, device=self.device)
+        viol = torch.empty((S, 5), dtype=torch.float64, device=self.device)
         N.check(N.lib().sf_feasibility(self._h, ctypes.byref(batch.c), prec, _ptr(xi), _ptr(bvals), _ptr(viol),
                                        _stream_ptr(stream)))
         return viol

@@ -31,8 +31,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_header_struct_layout_matches_binding():
-    assert ctypes.sizeof(N.SfConfig) == 4 * 4 + 8 * 8
+    assert ctypes.sizeof(N.SfConfig) == 4 * 4 + 14 * 8
     assert N.SfConfig.t_final.offset == 16
+    assert N.SfConfig.ws_a.offset == 16 + 8 * 8 and N.SfConfig.ws_z.offset == 16 + 13 * 8
 
 
 CFGS = [
@@ -41,10 +42,13 @@ CFGS = [
     W.cfg_swarm(32, degree=12, horizon=120),
     W.SwarmConfig(n_robots=3, dims=3, degree=7, horizon=12, t_final=4.0, safety_a=0.3, safety_b=0.5,
                   vmax=1.5, amax=0.0, rho_coll=0.7, rho_vel=1.3, rho_acc=1.0),
+    W.SwarmConfig(n_robots=4, dims=3, degree=9, horizon=20, t_final=6.0, safety_a=0.3, safety_b=0.3,
+                  vmax=1.5, amax=2.0, rho_coll=0.8, rho_vel=1.0, rho_acc=1.1,
+                  ws_a=2.0, ws_b=0.8, rho_ws=0.6, ws_x=0.3, ws_y=-0.2, ws_z=0.1),
 ]
 
 
-@pytest.mark.parametrize("cfg", CFGS, ids=["tiny2d", "n16", "n32deg12", "spheroid_novacc"])
+@pytest.mark.parametrize("cfg", CFGS, ids=["tiny2d", "n16", "n32deg12", "spheroid_novacc", "workspace"])
 def test_factor_table_matches_dense_kkt(cfg):
     ft = factor_table(cfg)
     s = O.build_system(cfg)
@@ -94,6 +98,18 @@ def test_factor_table_rejects_bad_configs(field, value, code):
     rc = N.lib().sf_factor_table(ctypes.byref(c), None, 0, ctypes.byref(need))
     assert rc == code
     assert len(N.lib().sf_last_error()) > 0
+
+
+@pytest.mark.parametrize("field,value", [("ws_b", 0.0), ("rho_ws", 0.0), ("ws_x", float("nan"))])
+def test_factor_table_rejects_bad_workspace(field, value):
+    base = N.make_config(CFGS[-1])
+    need = ctypes.c_int64()
+    assert N.lib().sf_factor_table(ctypes.byref(base), None, 0, ctypes.byref(need)) == N.SF_OK
+    setattr(base, field, value)
+    assert N.lib().sf_factor_table(ctypes.byref(base), None, 0, ctypes.byref(need)) == N.SF_EINVAL
+    # with the workspace off (ws_a <= 0) its other fields are ignored
+    base.ws_a = 0.0
+    assert N.lib().sf_factor_table(ctypes.byref(base), None, 0, ctypes.byref(need)) == N.SF_OK
 
 
 def test_factor_table_capacity_check():
