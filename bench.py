@@ -7,7 +7,8 @@ beside it on the same inputs, and both are judged at the same final feasibility 
 Prints one JSON line.
 
 Other workloads (not the headline): --workload swarm32 (32 robots, 4096 samples), swarm16ws (the
-16-robot workload with the workspace spheroid rows), ragged (3000 problems of 8/16/32 robots in
+16-robot workload with the workspace spheroid rows), swarm16sph (spheroidal robots, 0.3 m x 0.6 m
+keep-out), ragged (3000 problems of 8/16/32 robots in
 one persistent, graph-captured, autotuned launch) and diff16 (forward with checkpoints +
 adjoint, gradient evaluations per second).
 """
@@ -185,6 +186,8 @@ def run_single(args, wl):
     if ws:
         config["workspace"] = {"semi_axes": [p.cfg.ws_a, p.cfg.ws_a, p.cfg.ws_b],
                                "centre": [p.cfg.ws_x, p.cfg.ws_y, p.cfg.ws_z]}
+    if p.cfg.safety_b != p.cfg.safety_a:
+        config["safety_semi_axes"] = [p.cfg.safety_a, p.cfg.safety_a, p.cfg.safety_b]
     line = base_line(args, f"converged SF projections/sec ({p.cfg.n_robots} robots, 3D{', workspace' if ws else ''}); "
                      "BF16-MFMA vs FP32 at equal residual", n_conv / (ms / 1e3), ms, DTYPES[prec], config)
     line.update({"converged_fraction": round(n_conv / S, 6), "violation_p99": p99, "violation_max": vmax,
@@ -269,7 +272,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="swarm16",
-                    choices=["swarm16", "swarm16ws", "swarm32", "tiny2d", "ragged", "diff16"])
+                    choices=["swarm16", "swarm16ws", "swarm16sph", "swarm32", "tiny2d", "ragged", "diff16"])
     ap.add_argument("--precision", default="bf16", choices=["fp64", "fp32", "bf16", "fp16"])
     ap.add_argument("--compare", default="fp32", choices=["fp32", "bf16", "fp16", "none"],
                     help="second form timed beside the headline one")

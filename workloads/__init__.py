@@ -178,6 +178,14 @@ def swarm16ws(n_samples: int = 1024, iters: int = 300) -> Workload:
     return Workload("swarm16ws_3d", [p], iters=iters, precision="fp32")
 
 
+def swarm16sph(n_samples: int = 1024, iters: int = 300) -> Workload:
+    """The 16-robot instance with spheroidal robots: centre-to-centre semi-axes 0.3 m in x and y
+    and 0.6 m in z (a taller keep-out, as for the downwash below a quadrotor)."""
+    cfg = replace(cfg_swarm(16), safety_b=2 * SEP)
+    p = box_problem(cfg, n_samples, 0.4, seed=2)
+    return Workload("swarm16sph_3d", [p], iters=iters, precision="fp32")
+
+
 def swarm32(n_samples: int = 4096, iters: int = 300) -> Workload:
     """32 robots in 3D, degree 12, H 120, 4096 samples, 300 iterations."""
     p = box_problem(cfg_swarm(32, degree=12, horizon=120), n_samples, 0.4, seed=4)
@@ -224,6 +232,7 @@ WORKLOADS = {
     "tiny2d": tiny2d,
     "swarm16": swarm16,
     "swarm16ws": swarm16ws,
+    "swarm16sph": swarm16sph,
     "ragged": ragged,
     "swarm32": swarm32,
     "diff16": diff16,
