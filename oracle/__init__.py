@@ -15,6 +15,7 @@ from .sf_oracle import (  # noqa: F401
     project_workspace,
     sf_project,
     feasibility,
+    qp_equality,
     to_paper_order,
     from_paper_order,
 )

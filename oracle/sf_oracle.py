@@ -309,6 +309,18 @@ def sf_project(sys: OracleSystem, xi_bar: torch.Tensor, bvals: torch.Tensor, ite
     return from_paper_order(xi, n, m), from_paper_order(lam, n, m), resid
 
 
+def qp_equality(sys: OracleSystem, xi_in: torch.Tensor, bvals: torch.Tensor) -> torch.Tensor:
+    """Equality-only QP layer of the decoders (Sec. IV: the QP of eq. (sf_form) without its
+    inequality rows): argmin 1/2 ||xi - xi_in||^2 subject to the boundary rows A xi = b of
+    eq. (boundary_con), per robot-axis, by its definition xi_in - A^T (A A^T)^{-1} (A xi_in - b).
+    xi_in [B, n, D, m], bvals [n, D, 6] -> [B, n, D, m] float64 (differentiable)."""
+    A1 = sys.A[:6, :sys.m]                                            # one robot-axis block
+    xi = xi_in.to(DT)
+    r = torch.einsum("rk,bidk->bidr", A1, xi) - bvals.to(DT)[None]
+    mu = torch.linalg.solve(A1 @ A1.T, r.unsqueeze(-1)).squeeze(-1)
+    return xi - torch.einsum("rk,bidr->bidk", A1, mu)
+
+
 def _resid_pair(sys: OracleSystem, rp: torch.Tensor) -> torch.Tensor:
     return torch.stack([(rp * rp).sum((1, 2)), _block_norm_max(sys, rp)], dim=1)
 

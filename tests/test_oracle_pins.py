@@ -413,6 +413,68 @@ def test_equality_only_limit_is_the_affine_projection():
     assert np.abs(lam.numpy()).max() < 1e-12     # the trig closed forms rebuild r to rounding
 
 
+# --------------------------------------------------------------------------
+# equality-only QP layer of the decoders (the QP of eq. (sf_form) without inequalities)
+# --------------------------------------------------------------------------
+
+def test_qp_equality_is_the_orthogonal_projection_onto_the_boundary_conditions():
+    # the minimiser of 1/2||xi - xi_in||^2 on {A xi = b} is the unique point of that affine set
+    # whose offset from xi_in lies in the row space of A: check both with scipy's null space,
+    # idempotence, and that only the three first and last coefficients move
+    cfg = small_cfg(n=3, D=3, degree=9, H=15, T=4.0)
+    s = O.build_system(cfg)
+    rng = np.random.default_rng(21)
+    xi_in = rng.normal(size=(4, 3, 3, 10))
+    b = rng.normal(size=(3, 3, 6))
+    out = O.qp_equality(s, torch.tensor(xi_in), torch.tensor(b)).numpy()
+    A1 = s.A.numpy()[:6, :10]
+    assert np.allclose(np.einsum("rk,bidk->bidr", A1, out), b[None], atol=1e-10)
+    Z = scipy.linalg.null_space(A1)
+    assert np.abs(np.einsum("kz,bidk->bidz", Z, xi_in - out)).max() < 1e-11
+    again = O.qp_equality(s, torch.tensor(out), torch.tensor(b)).numpy()
+    assert np.allclose(again, out, atol=1e-11)
+    assert np.allclose(out[..., 3:-3], xi_in[..., 3:-3], atol=1e-12)
+    # against a generic equality-constrained least-squares solve (scipy lstsq on the KKT system)
+    K = np.block([[np.eye(10), A1.T], [A1, np.zeros((6, 6))]])
+    for bi in range(2):
+        for i in range(3):
+            for d in range(3):
+                sol = np.linalg.lstsq(K, np.concatenate([xi_in[bi, i, d], b[i, d]]), rcond=None)[0][:10]
+                assert np.allclose(out[bi, i, d], sol, atol=1e-10)
+
+
+def test_qp_equality_is_the_sf_limit_without_active_inequalities():
+    # with every inequality inactive the SF iteration converges to the same projection
+    cfg = small_cfg(n=3, D=2, degree=8, H=12, T=3.0, vmax=0.0, amax=0.0, rho=(0.05, 1, 1))
+    rng = np.random.default_rng(6)
+    st = np.array([[0.0, 0.0], [5.0, 0.0], [10.0, 0.0]])
+    gl = st + np.array([0.0, 1.0])
+    xi_bar = W.straight_line_coeffs(st, gl, cfg.degree)[None] + rng.normal(size=(1, 3, 2, 9)) * 0.05
+    b = W.boundary_values(st, gl)
+    s = O.build_system(cfg)
+    out, _, _ = O.sf_project(s, torch.tensor(xi_bar), torch.tensor(b), 400)
+    q = O.qp_equality(s, torch.tensor(xi_bar), torch.tensor(b))
+    assert torch.allclose(out, q, atol=1e-10)
+
+
+def test_qp_equality_gradient_matches_central_differences():
+    cfg = small_cfg(n=2, D=3, degree=7, H=10)
+    s = O.build_system(cfg)
+    rng = np.random.default_rng(22)
+    xi = torch.tensor(rng.normal(size=(2, 2, 3, 8)), requires_grad=True)
+    b = torch.tensor(rng.normal(size=(2, 3, 6)), requires_grad=True)
+    w = torch.tensor(rng.normal(size=(2, 2, 3, 8)))
+    loss = (O.qp_equality(s, xi, b) * w).sum()
+    gx, gb = torch.autograd.grad(loss, (xi, b))
+    for _ in range(3):
+        dx = torch.tensor(rng.normal(size=xi.shape))
+        db = torch.tensor(rng.normal(size=b.shape))
+        h = 1e-6
+        f = lambda t: (O.qp_equality(s, xi.detach() + t * dx, b.detach() + t * db) * w).sum().item()
+        fd = (f(h) - f(-h)) / (2 * h)
+        assert abs(fd - ((gx * dx).sum() + (gb * db).sum()).item()) < 1e-7 * (1 + abs(fd))
+
+
 def test_boundary_conditions_hold_after_each_iteration():
     wl = W.tiny2d(3)
     p = wl.problems[0]
