@@ -8,7 +8,8 @@ Prints one JSON line.
 
 Other workloads (not the headline): --workload swarm32 (32 robots, 4096 samples), swarm16ws (the
 16-robot workload with the workspace spheroid rows), swarm16sph (spheroidal robots, 0.3 m x 0.6 m
-keep-out), ragged (3000 problems of 8/16/32 robots in
+keep-out), eqqp16 (the decoders' equality-only QP layer over 2^20 samples), ragged (3000 problems of
+8/16/32 robots in
 one persistent, graph-captured, autotuned launch) and diff16 (forward with checkpoints +
 adjoint, gradient evaluations per second).
 """
@@ -153,6 +154,59 @@ def base_line(args, metric, value, ms, dtype, config, scaling="weak"):
             "data": "synthetic (seeded straight-line Bernstein fits + Gaussian coefficient noise)", "config": config}
 
 
+def run_eqqp(args, wl):
+    """Equality-only QP layer (sf_qp_equality) over 2^20 decoder outputs of the 16-robot shape:
+    forward timed; the reverse mode timed beside it.  HBM-bound: each call reads and writes every
+    coefficient once."""
+    import torch
+    import paper_2501_19042_amd as P
+    p = wl.problems[0]
+    S = int(wl.notes.split("=")[1])
+    prec = "fp64" if args.precision == "fp64" else "fp32"
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    sf = P.SafetyFilter([p.cfg])
+    import workloads as W
+    base = torch.tensor(W.straight_line_coeffs(p.starts, p.goals, p.cfg.degree), dtype=dt, device="cuda")
+    g = torch.Generator(device="cuda").manual_seed(2)
+    xi = base[None] + 0.4 * torch.randn((S,) + tuple(base.shape), generator=g, dtype=dt, device="cuda")
+    bv = torch.tensor(p.bvals, dtype=dt, device="cuda")
+    out = torch.empty_like(xi)
+    ms, _ = time_calls(lambda: P.qp_equality(sf, xi, bv, precision=prec, out=out), args.steps, args.warmup)
+    import ctypes
+    from paper_2501_19042_amd import _native as N
+    batch = sf._batch(None, xi)
+    g_in = torch.empty_like(xi)
+    g_b = torch.empty_like(bv)
+    bw = lambda: N.check(N.lib().sf_qp_equality_backward(sf._h, ctypes.byref(batch.c), N.PRECISIONS[prec],
+                                                         out.data_ptr(), g_in.data_ptr(), g_b.data_ptr(), None))
+    ms_b, _ = time_calls(bw, args.steps, args.warmup)
+    nDm = p.cfg.n_robots * p.cfg.dims * p.cfg.m
+    esz = 8 if prec == "fp64" else 4
+    algo = 2 * S * nDm * esz + bv.numel() * esz
+    line = base_line(args, f"equality-only QP layer projections/sec ({p.cfg.n_robots} robots, 3D)", S / (ms / 1e3),
+                     ms, "f64" if prec == "fp64" else "f32",
+                     {"workload": wl.name, "samples": S, "robots": p.cfg.n_robots, "dims": p.cfg.dims,
+                      "degree": p.cfg.degree, "precision": prec})
+    line["data"] = "synthetic (straight-line Bernstein fits + seeded N(0, 0.4) coefficient noise drawn on the device)"
+    line["roofline"] = {"bound": "hbm", "achieved": round(algo / (ms / 1e3) / 1e9, 1), "peak": 8000.0,
+                        "unit": "GB/s", "frac": round(algo / (ms / 1e3) / 1e9 / 8000.0, 4), "traffic": None,
+                        "bytes_per_launch": algo, "kernel_ms": round(ms, 4)}
+    line["reverse_mode"] = {"ms_per_call": round(ms_b, 4),
+                            "achieved_GBps": round((2 * S * nDm * esz) / (ms_b / 1e3) / 1e9, 1)}
+    if not args.no_cpu_baseline:
+        import oracle as O
+        n_cpu = min(S, args.cpu_samples * 1024)
+        xs = xi[:n_cpu].double().cpu()
+        s = O.build_system(p.cfg)
+        t0 = time.perf_counter()
+        O.qp_equality(s, xs, bv.double().cpu())
+        dtc = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": round(n_cpu / dtc, 1), "unit": "projections/s",
+                                "cores": torch.get_num_threads(), "kind": "oracle",
+                                "sample": f"first {n_cpu} of {S} samples, FP64 torch CPU ({dtc:.2f} s)"}
+    return line
+
+
 def run_single(args, wl):
     """One problem with many samples (16- or 32-robot swarm): headline form + comparison form."""
     import torch
@@ -272,7 +326,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="swarm16",
-                    choices=["swarm16", "swarm16ws", "swarm16sph", "swarm32", "tiny2d", "ragged", "diff16"])
+                    choices=["swarm16", "swarm16ws", "swarm16sph", "eqqp16", "swarm32", "tiny2d", "ragged",
+                             "diff16"])
     ap.add_argument("--precision", default="bf16", choices=["fp64", "fp32", "bf16", "fp16"])
     ap.add_argument("--compare", default="fp32", choices=["fp32", "bf16", "fp16", "none"],
                     help="second form timed beside the headline one")
@@ -307,6 +362,8 @@ def main():
         line = run_ragged(args, wl)
     elif args.workload == "diff16":
         line = run_diff(args, wl)
+    elif args.workload == "eqqp16":
+        line = run_eqqp(args, wl)
     else:
         line = run_single(args, wl)
     print(json.dumps(line), flush=True)

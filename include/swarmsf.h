@@ -148,6 +148,30 @@ sf_status sf_project_backward(sf_handle h, const sf_batch* batch, int32_t precis
 sf_status sf_feasibility(sf_handle h, const sf_batch* batch, int32_t precision,
                          const void* xi, const void* bvals, void* viol_out, void* stream);
 
+/* Equality-only QP layer of the decoders (Sec. IV: the QP of eq. sf_form without its inequality
+ * rows, solved in closed form):
+ *   xi_out = argmin 1/2 ||xi - xi_in||^2  subject to the boundary rows A xi = b of eq. boundary_con.
+ * Those rows involve only the three first and three last coefficients of each robot-axis (the
+ * Bernstein end conditions), so the other coefficients pass through and those six become Bmap b
+ * (the inverse end-condition block sf_setup stores, see sf_factor_table).
+ *  xi_in   [S, n, D, m]  device; double for SF_FP64, float for any other precision
+ *  bvals   [P, n, D, 6]  device, boundary values per problem, as for sf_project
+ *  xi_out  [S, n, D, m]  device; may be xi_in itself (in place), must not overlap it otherwise
+ * The workspace, bounds and penalty weights of the configs play no part.  Errors: SF_EINVAL for
+ * NULL or misaligned arrays and bad batches; launch failures as for sf_project. */
+sf_status sf_qp_equality(sf_handle h, const sf_batch* batch, int32_t precision, const void* xi_in,
+                         const void* bvals, void* xi_out, void* stream);
+
+/* Reverse mode of sf_qp_equality for cotangents g_out [S, n, D, m] of xi_out:
+ *  g_xi_in [S, n, D, m]  g_out with the six end coefficients of every robot-axis zeroed, or NULL
+ *                        (may be g_out itself)
+ *  g_bvals [P, n, D, 6]  per problem, the sum over its samples of Bmap^T g_out[end coefficients],
+ *                        summed in a fixed order (deterministic), or NULL
+ * Calls on one handle must not overlap in time on different streams: the per-sample-chunk
+ * partial sums of g_bvals live in a scratch buffer the handle owns (grown on demand). */
+sf_status sf_qp_equality_backward(sf_handle h, const sf_batch* batch, int32_t precision, const void* g_out,
+                                  void* g_xi_in, void* g_bvals, void* stream);
+
 /* Host-only inspection of the FP64 factor table sf_setup builds for one config (needs no
  * GPU).  Writes a 16-double header (m, m_f, H, n, then element offsets of basis, X1, X01,
  * Bmap, Gfx, Rfx into the table that follows) and the table; *needed receives the

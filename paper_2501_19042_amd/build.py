@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libswarmsf.so")
-SOURCES = ["sf_api.hip", "sf_generic.hip", "sf_fast.hip", "sf_adjoint.hip"]
+SOURCES = ["sf_api.hip", "sf_generic.hip", "sf_fast.hip", "sf_adjoint.hip", "sf_eqqp.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -4,6 +4,7 @@
 #include "sf_internal.h"
 #include "sf_fast.h"
 #include "sf_adjoint.h"
+#include "sf_eqqp.h"
 
 #include <algorithm>
 #include <cmath>
@@ -228,6 +229,10 @@ struct Plan {
   std::vector<sf::WorkItem> items;      // host copy of the work items
   sf::FastPlan fast;            // MFMA-path plan (empty if not applicable)
   sf::FastPlan fast_persistent; // persistent launch of a single-shape batch (built on request)
+  // equality-only QP layer: sample chunks per problem (built on first use)
+  sf::WorkItem* d_eq_chunks = nullptr;
+  int32_t* d_eq_chunk_first = nullptr;
+  int32_t n_eq_chunks = 0;
   struct GraphEntry {
     std::vector<uintptr_t> key;
     hipGraphExec_t exec = nullptr;
@@ -241,6 +246,8 @@ struct sf_handle_s {
   int device = 0;
   void* scratch = nullptr;       // adjoint recompute states, grown on demand
   size_t scratch_bytes = 0;
+  void* eq_part = nullptr;       // per-chunk partial sums of the equality layer's reverse mode
+  size_t eq_part_bytes = 0;
   std::vector<HostCfg> cfgs;
   sf::DevCfg* d_cfgs = nullptr;
   double* d_tab64 = nullptr;
@@ -259,6 +266,8 @@ void free_plan(Plan* p) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (p->d_probs) (void)hipFree(p->d_probs);
   if (p->d_items) (void)hipFree(p->d_items);
+  if (p->d_eq_chunks) (void)hipFree(p->d_eq_chunks);
+  if (p->d_eq_chunk_first) (void)hipFree(p->d_eq_chunk_first);
   sf::fast_plan_free(p->fast);
   sf::fast_plan_free(p->fast_persistent);
   delete p;
@@ -504,6 +513,38 @@ sf_status autotune(sf_handle h, const Plan* p, sf::FastPlan& fp, const sf::Launc
   return SF_OK;
 }
 
+// Sample chunks of the equality-only QP layer: each problem's samples in runs of about 32K
+// coefficients (one workgroup each), and the first chunk of every problem.
+sf_status get_eq_chunks(sf_handle h, Plan* p) {
+  if (p->d_eq_chunks) return SF_OK;
+  std::vector<sf::WorkItem> ch;
+  std::vector<int32_t> first;
+  for (size_t q = 0; q < p->probs.size(); ++q) {
+    const sf::DevProblem& pr = p->probs[q];
+    const sf::DevCfg& c = h->cfgs[pr.cfg].dev;
+    const int per = std::max(1, 32768 / (c.n * c.D * c.m));
+    first.push_back((int32_t)ch.size());
+    for (int s = 0; s < pr.count; s += per) ch.push_back(sf::WorkItem{(int32_t)q, s, std::min(per, pr.count - s), 0});
+  }
+  first.push_back((int32_t)ch.size());
+  if (ch.size() > (size_t)INT32_MAX) return fail(SF_EUNSUPPORTED, "too many sample chunks");
+  hipError_t e = hipMalloc(&p->d_eq_chunks, ch.size() * sizeof(sf::WorkItem));
+  if (e == hipSuccess) e = hipMalloc(&p->d_eq_chunk_first, first.size() * sizeof(int32_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_eq_chunks, ch.data(), ch.size() * sizeof(sf::WorkItem), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_eq_chunk_first, first.data(), first.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (p->d_eq_chunks) (void)hipFree(p->d_eq_chunks);
+    if (p->d_eq_chunk_first) (void)hipFree(p->d_eq_chunk_first);
+    p->d_eq_chunks = nullptr;
+    p->d_eq_chunk_first = nullptr;
+    return hip_fail(e, "equality layer chunk table");
+  }
+  p->n_eq_chunks = (int32_t)ch.size();
+  return SF_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------
@@ -611,6 +652,7 @@ void sf_destroy(sf_handle h) {
   if (h->d_a16) (void)hipFree(h->d_a16);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->scratch) (void)hipFree(h->scratch);
+  if (h->eq_part) (void)hipFree(h->eq_part);
   delete h;
 }
 
@@ -810,6 +852,103 @@ sf_status sf_feasibility(sf_handle h, const sf_batch* batch, int32_t precision, 
                                         precision == SF_FP64, bvals, static_cast<double*>(viol_out), tile, lds,
                                         static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "sf_feasibility launch");
+  return SF_OK;
+}
+
+sf_status sf_qp_equality(sf_handle h, const sf_batch* batch, int32_t precision, const void* xi_in,
+                         const void* bvals, void* xi_out, void* stream) {
+  g_err.clear();
+  if (!h) return fail(SF_EINVAL, "handle is NULL");
+  if (!xi_in || !bvals || !xi_out) return fail(SF_EINVAL, "xi_in, bvals and xi_out are required");
+  if (precision < SF_FP64 || precision > SF_FP16) return fail(SF_EINVAL, "unknown precision");
+  const size_t elem = precision == SF_FP64 ? sizeof(double) : sizeof(float);
+  if (!aligned(xi_in, elem) || !aligned(bvals, elem) || !aligned(xi_out, elem))
+    return fail(SF_EINVAL, "misaligned array");
+  std::lock_guard<std::mutex> lock(h->mu);
+  sf_status st = check_device(h);
+  if (st != SF_OK) return st;
+  Plan* p = nullptr;
+  st = get_plan(h, batch, &p);
+  if (st == SF_OK) st = get_eq_chunks(h, p);
+  if (st != SF_OK) return st;
+  sf::EqArgs a{};
+  a.cfgs = h->d_cfgs;
+  a.probs = p->d_probs;
+  a.n_probs = (int32_t)p->probs.size();
+  a.chunks = p->d_eq_chunks;
+  a.n_chunks = p->n_eq_chunks;
+  a.forward = true;
+  a.in = xi_in;
+  a.bvals = bvals;
+  a.out = xi_out;
+  for (int32_t s : p->slots_used) a.lds_bytes = std::max(a.lds_bytes, sf::qp_equality_lds_bytes(h->cfgs[s].dev, elem));
+  a.stream = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (precision == SF_FP64) {
+    a.tab = h->d_tab64;
+    e = sf::launch_qp_equality<double>(a);
+  } else {
+    a.tab = h->d_tab32;
+    e = sf::launch_qp_equality<float>(a);
+  }
+  if (e != hipSuccess) return hip_fail(e, "sf_qp_equality launch");
+  return SF_OK;
+}
+
+sf_status sf_qp_equality_backward(sf_handle h, const sf_batch* batch, int32_t precision, const void* g_out,
+                                  void* g_xi_in, void* g_bvals, void* stream) {
+  g_err.clear();
+  if (!h) return fail(SF_EINVAL, "handle is NULL");
+  if (!g_out) return fail(SF_EINVAL, "g_out is required");
+  if (precision < SF_FP64 || precision > SF_FP16) return fail(SF_EINVAL, "unknown precision");
+  const size_t elem = precision == SF_FP64 ? sizeof(double) : sizeof(float);
+  if (!aligned(g_out, elem) || (g_xi_in && !aligned(g_xi_in, elem)) || (g_bvals && !aligned(g_bvals, elem)))
+    return fail(SF_EINVAL, "misaligned array");
+  if (!g_xi_in && !g_bvals) return SF_OK;
+  std::lock_guard<std::mutex> lock(h->mu);
+  sf_status st = check_device(h);
+  if (st != SF_OK) return st;
+  Plan* p = nullptr;
+  st = get_plan(h, batch, &p);
+  if (st == SF_OK) st = get_eq_chunks(h, p);
+  if (st != SF_OK) return st;
+  int32_t stride = 0;
+  for (int32_t s : p->slots_used) stride = std::max(stride, h->cfgs[s].dev.n * h->cfgs[s].dev.D * sf::kNFix);
+  if (g_bvals) {
+    const size_t need = (size_t)p->n_eq_chunks * stride * elem;
+    if (need > h->eq_part_bytes) {
+      if (h->eq_part) (void)hipFree(h->eq_part);
+      h->eq_part = nullptr;
+      h->eq_part_bytes = 0;
+      if (hipMalloc(&h->eq_part, need) != hipSuccess) return fail(SF_ENOMEM, "equality layer scratch allocation failed");
+      h->eq_part_bytes = need;
+    }
+  }
+  sf::EqArgs a{};
+  a.cfgs = h->d_cfgs;
+  a.probs = p->d_probs;
+  a.n_probs = (int32_t)p->probs.size();
+  a.chunks = p->d_eq_chunks;
+  a.n_chunks = p->n_eq_chunks;
+  a.chunk_first = p->d_eq_chunk_first;
+  a.forward = false;
+  a.in = g_out;
+  a.out = g_xi_in;
+  a.part = g_bvals ? h->eq_part : nullptr;
+  a.part_stride = stride;
+  a.max_rows = stride / sf::kNFix;
+  a.g_bvals = g_bvals;
+  for (int32_t s : p->slots_used) a.lds_bytes = std::max(a.lds_bytes, sf::qp_equality_lds_bytes(h->cfgs[s].dev, elem));
+  a.stream = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (precision == SF_FP64) {
+    a.tab = h->d_tab64;
+    e = sf::launch_qp_equality<double>(a);
+  } else {
+    a.tab = h->d_tab32;
+    e = sf::launch_qp_equality<float>(a);
+  }
+  if (e != hipSuccess) return hip_fail(e, "sf_qp_equality_backward launch");
   return SF_OK;
 }
 

@@ -155,6 +155,50 @@ class SafetyFilter:
         return viol
 
 
+def _eq_dtype(precision):
+    return torch.float64 if N.PRECISIONS[precision] == N.SF_FP64 else torch.float32
+
+
+def qp_equality(sf: "SafetyFilter", xi_in: torch.Tensor, bvals: torch.Tensor, batch: Optional[Batch] = None,
+                precision: str = "fp32", out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Equality-only QP layer (sf_qp_equality): xi_in with the boundary conditions imposed."""
+    prec = N.PRECISIONS[precision]
+    batch = sf._batch(batch, xi_in)
+    S, coef, bnd = sf.sizes(batch)
+    sf._check(xi_in, "xi_in", _eq_dtype(precision), coef)
+    sf._check(bvals, "bvals", _eq_dtype(precision), bnd)
+    xo = torch.empty_like(xi_in) if out is None else out
+    N.check(N.lib().sf_qp_equality(sf._h, ctypes.byref(batch.c), prec, _ptr(xi_in), _ptr(bvals), _ptr(xo),
+                                   _stream_ptr(stream)))
+    return xo
+
+
+class _QPEquality(torch.autograd.Function):
+    """sf_qp_equality forward, sf_qp_equality_backward reverse."""
+
+    @staticmethod
+    def forward(ctx, xi_in, bvals, sf, batch, precision):
+        ctx.cfg = (sf, batch, precision, bvals.shape)
+        return qp_equality(sf, xi_in.detach().contiguous(), bvals.detach().contiguous(), batch, precision)
+
+    @staticmethod
+    def backward(ctx, g_out):
+        sf, batch, precision, bshape = ctx.cfg
+        g_out = g_out.contiguous()
+        g_in = torch.empty_like(g_out) if ctx.needs_input_grad[0] else None
+        g_b = torch.empty(bshape, dtype=g_out.dtype, device=g_out.device) if ctx.needs_input_grad[1] else None
+        N.check(N.lib().sf_qp_equality_backward(sf._h, ctypes.byref(sf._batch(batch, g_out).c),
+                                                N.PRECISIONS[precision], _ptr(g_out), _ptr(g_in), _ptr(g_b),
+                                                _stream_ptr(None)))
+        return g_in, g_b, None, None, None
+
+
+def qp_equality_differentiable(sf: "SafetyFilter", xi_in: torch.Tensor, bvals: torch.Tensor,
+                               batch: Optional[Batch] = None, precision: str = "fp32") -> torch.Tensor:
+    """The decoders' QP layer as an autograd function: gradients flow to xi_in and bvals."""
+    return _QPEquality.apply(xi_in, bvals, sf, batch, precision)
+
+
 def factor_table(cfg):
     """Host FP64 factor table of one config (no GPU needed); see sf_factor_table."""
     c = N.make_config(cfg)

@@ -186,6 +186,15 @@ def swarm16sph(n_samples: int = 1024, iters: int = 300) -> Workload:
     return Workload("swarm16sph_3d", [p], iters=iters, precision="fp32")
 
 
+def eqqp16(n_samples: int = 1 << 20) -> Workload:
+    """Decoder outputs for the equality-only QP layer: the 16-robot instance's straight-line
+    coefficients plus N(0, 0.4) noise on every coefficient (so the end coefficients miss the
+    boundary values).  Only 8 samples are drawn here; the benchmark draws the full batch of
+    n_samples on the device from a seeded generator, in the same form."""
+    p = box_problem(cfg_swarm(16), 8, 0.4, seed=2)
+    return Workload("eqqp16_3d", [p], iters=0, precision="fp32", notes=f"n_samples={n_samples}")
+
+
 def swarm32(n_samples: int = 4096, iters: int = 300) -> Workload:
     """32 robots in 3D, degree 12, H 120, 4096 samples, 300 iterations."""
     p = box_problem(cfg_swarm(32, degree=12, horizon=120), n_samples, 0.4, seed=4)
@@ -233,6 +242,7 @@ WORKLOADS = {
     "swarm16": swarm16,
     "swarm16ws": swarm16ws,
     "swarm16sph": swarm16sph,
+    "eqqp16": eqqp16,
     "ragged": ragged,
     "swarm32": swarm32,
     "diff16": diff16,
