@@ -17,6 +17,10 @@ namespace {
 
 constexpr int kEqBlock = 256;
 
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float4 type; };
+template <> struct Vec16<double> { typedef double2 type; };
+
 // LDS per workgroup: pinned values [nD][6] (T) and the position table [nDm] (int).
 template <typename T>
 __device__ void eq_tables(const DevCfg& c, const T* __restrict__ Bmap, const T* __restrict__ bv, T* pin, int* tbl) {
@@ -52,15 +56,38 @@ qp_equality_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, c
     __syncthreads();
     const int64_t base = pr.coef_off + (int64_t)w.first * nDm;
     const int64_t total = (int64_t)w.count * nDm;
-    // position within the sample, advanced without a division per element
-    const int step = kEqBlock % nDm;
-    int e = threadIdx.x % nDm;
-    for (int64_t idx = threadIdx.x; idx < total; idx += kEqBlock) {
-      const T v = xin[base + idx];
-      const int p = tbl[e];
-      xout[base + idx] = p < 0 ? v : pin[p];
-      e += step;
-      if (e >= nDm) e -= nDm;
+    constexpr int VW = 16 / sizeof(T);           // elements per 16-byte access
+    const bool vec = (nDm % VW) == 0 && ((uintptr_t)(xin + base) % 16) == 0 && ((uintptr_t)(xout + base) % 16) == 0;
+    if (vec) {
+      // 16-byte accesses: VW consecutive positions of one sample per access
+      typedef typename Vec16<T>::type V;
+      const int nV = nDm / VW, stepV = kEqBlock % nV;
+      int ev = threadIdx.x % nV;
+      const V* xv = reinterpret_cast<const V*>(xin + base);
+      V* ov = reinterpret_cast<V*>(xout + base);
+      for (int64_t idx = threadIdx.x; idx < total / VW; idx += kEqBlock) {
+        V v = xv[idx];
+        T* pv = reinterpret_cast<T*>(&v);
+#pragma unroll
+        for (int j = 0; j < VW; ++j) {
+          const int p = tbl[ev * VW + j];
+          pv[j] = p < 0 ? pv[j] : pin[p < 0 ? 0 : p];
+        }
+        ov[idx] = v;
+        ev += stepV;
+        if (ev >= nV) ev -= nV;
+      }
+    } else {
+      // position within the sample, advanced without a division per element
+      const int step = kEqBlock % nDm;
+      int e = threadIdx.x % nDm;
+      for (int64_t idx = threadIdx.x; idx < total; idx += kEqBlock) {
+        const T v = xin[base + idx];
+        const int p = tbl[e];
+        xout[base + idx] = p < 0 ? v : pin[p];
+        e += step;
+        if (e >= nDm) e -= nDm;
+      }
     }
     __syncthreads();
   }
@@ -85,13 +112,32 @@ qp_equality_bwd_kernel(const DevCfg* __restrict__ cfgs, const DevProblem* __rest
     __syncthreads();
     const int64_t base = pr.coef_off + (int64_t)w.first * nDm;
     const int64_t total = (int64_t)w.count * nDm;
-    const int step = kEqBlock % nDm;
-    int e = threadIdx.x % nDm;
-    for (int64_t idx = threadIdx.x; idx < total; idx += kEqBlock) {
-      const T v = g[base + idx];
-      g_in[base + idx] = keep[e] ? v : T(0);
-      e += step;
-      if (e >= nDm) e -= nDm;
+    constexpr int VW = 16 / sizeof(T);
+    const bool vec = (nDm % VW) == 0 && ((uintptr_t)(g + base) % 16) == 0 && ((uintptr_t)(g_in + base) % 16) == 0;
+    if (vec) {
+      typedef typename Vec16<T>::type V;
+      const int nV = nDm / VW, stepV = kEqBlock % nV;
+      int ev = threadIdx.x % nV;
+      const V* gv = reinterpret_cast<const V*>(g + base);
+      V* ov = reinterpret_cast<V*>(g_in + base);
+      for (int64_t idx = threadIdx.x; idx < total / VW; idx += kEqBlock) {
+        V v = gv[idx];
+        T* pv = reinterpret_cast<T*>(&v);
+#pragma unroll
+        for (int j = 0; j < VW; ++j) pv[j] = keep[ev * VW + j] ? pv[j] : T(0);
+        ov[idx] = v;
+        ev += stepV;
+        if (ev >= nV) ev -= nV;
+      }
+    } else {
+      const int step = kEqBlock % nDm;
+      int e = threadIdx.x % nDm;
+      for (int64_t idx = threadIdx.x; idx < total; idx += kEqBlock) {
+        const T v = g[base + idx];
+        g_in[base + idx] = keep[e] ? v : T(0);
+        e += step;
+        if (e >= nDm) e -= nDm;
+      }
     }
     __syncthreads();
   }
