@@ -65,14 +65,39 @@ qp_equality_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, c
       int ev = threadIdx.x % nV;
       const V* xv = reinterpret_cast<const V*>(xin + base);
       V* ov = reinterpret_cast<V*>(xout + base);
-      for (int64_t idx = threadIdx.x; idx < total / VW; idx += kEqBlock) {
-        V v = xv[idx];
+      const int64_t nvt = total / VW;
+      auto fix = [&](V& v, int at) {
         T* pv = reinterpret_cast<T*>(&v);
 #pragma unroll
         for (int j = 0; j < VW; ++j) {
-          const int p = tbl[ev * VW + j];
+          const int p = tbl[at * VW + j];
           pv[j] = p < 0 ? pv[j] : pin[p < 0 ? 0 : p];
         }
+      };
+      int64_t idx = threadIdx.x;
+      // four accesses in flight per thread: loads first, then the fix-ups and stores
+      for (; idx + 3 * kEqBlock < nvt; idx += 4 * kEqBlock) {
+        V v[4];
+        int at[4];
+        at[0] = ev;
+#pragma unroll
+        for (int u = 1; u < 4; ++u) {
+          at[u] = at[u - 1] + stepV;
+          if (at[u] >= nV) at[u] -= nV;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = xv[idx + u * kEqBlock];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          fix(v[u], at[u]);
+          ov[idx + u * kEqBlock] = v[u];
+        }
+        ev = at[3] + stepV;
+        if (ev >= nV) ev -= nV;
+      }
+      for (; idx < nvt; idx += kEqBlock) {
+        V v = xv[idx];
+        fix(v, ev);
         ov[idx] = v;
         ev += stepV;
         if (ev >= nV) ev -= nV;
