@@ -8,7 +8,8 @@ Prints one JSON line.
 
 Other workloads (not the headline): --workload swarm32 (32 robots, 4096 samples), swarm16ws (the
 16-robot workload with the workspace spheroid rows), swarm16sph (spheroidal robots, 0.3 m x 0.6 m
-keep-out), eqqp16 (the decoders' equality-only QP layer over 2^20 samples), ragged (3000 problems of
+keep-out), eqqp16 (the decoders' equality-only QP layer over 2^20 samples), warmstart16 (zero against
+sampled initialisation, converged fraction and residuals after 25..300 iterations), ragged (3000 problems of
 8/16/32 robots in
 one persistent, graph-captured, autotuned launch) and diff16 (forward with checkpoints +
 adjoint, gradient evaluations per second).
@@ -207,6 +208,42 @@ def run_eqqp(args, wl):
     return line
 
 
+def run_warmstart(args, wl):
+    """Warm-start study on the 16-robot workload: the SF from the sampled coefficients (xi0 = xi_bar,
+    the default) against a zero initialisation (xi0 = 0, lambda0 = 0), after K = 25 .. 300
+    iterations on the MFMA kernel: converged fraction and residual quantiles per K.  The timed
+    line is the sampled initialisation at the workload's K."""
+    import torch
+    from paper_2501_19042_amd import SafetyFilter
+    p = wl.problems[0]
+    prec = "fp32" if args.precision == "fp64" else args.precision
+    sf = SafetyFilter([p.cfg])
+    xb = torch.tensor(p.xi_bar, dtype=torch.float32, device="cuda")
+    bv = torch.tensor(p.bvals, dtype=torch.float32, device="cuda")
+    zero = torch.zeros_like(xb)
+    S = xb.shape[0]
+    curves = {}
+    for name, xi0, lam0 in (("sample_init", None, None), ("zero_init", zero, zero)):
+        rows = {}
+        for K in (25, 50, 100, 200, 300):
+            out = sf.project(xb, bv, K, precision=prec, xi0=xi0, lam0=lam0)
+            torch.cuda.synchronize()
+            n_conv, p99, vmax = judge(sf, out.xi, bv, prec)
+            r = out.resid[:, 0].double().cpu()
+            rows[str(K)] = {"converged_fraction": round(n_conv / S, 4),
+                            "resid_sq_median": float(r.median()), "resid_sq_p90": float(r.quantile(0.9)),
+                            "violation_p99": p99}
+        curves[name] = rows
+    ms, out = time_calls(lambda: sf.project(xb, bv, wl.iters, precision=prec), args.steps, args.warmup)
+    n_conv, _, _ = judge(sf, out.xi, bv, prec)
+    line = base_line(args, f"converged SF projections/sec ({p.cfg.n_robots} robots, 3D); warm-start study",
+                     n_conv / (ms / 1e3), ms, DTYPES[prec],
+                     {"workload": "warmstart16_3d", "samples": S, "robots": p.cfg.n_robots, "iters": wl.iters,
+                      "precision": prec})
+    line["warm_start_study"] = curves
+    return line
+
+
 def run_single(args, wl):
     """One problem with many samples (16- or 32-robot swarm): headline form + comparison form."""
     import torch
@@ -326,8 +363,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="swarm16",
-                    choices=["swarm16", "swarm16ws", "swarm16sph", "eqqp16", "swarm32", "tiny2d", "ragged",
-                             "diff16"])
+                    choices=["swarm16", "swarm16ws", "swarm16sph", "eqqp16", "warmstart16", "swarm32", "tiny2d",
+                             "ragged", "diff16"])
     ap.add_argument("--precision", default="bf16", choices=["fp64", "fp32", "bf16", "fp16"])
     ap.add_argument("--compare", default="fp32", choices=["fp32", "bf16", "fp16", "none"],
                     help="second form timed beside the headline one")
@@ -357,13 +394,15 @@ def main():
 
     import workloads as W
     torch.cuda.set_device(0)
-    wl = W.WORKLOADS[args.workload]()
+    wl = W.WORKLOADS["swarm16" if args.workload == "warmstart16" else args.workload]()
     if args.workload == "ragged":
         line = run_ragged(args, wl)
     elif args.workload == "diff16":
         line = run_diff(args, wl)
     elif args.workload == "eqqp16":
         line = run_eqqp(args, wl)
+    elif args.workload == "warmstart16":
+        line = run_warmstart(args, wl)
     else:
         line = run_single(args, wl)
     print(json.dumps(line), flush=True)

@@ -206,6 +206,24 @@ def test_fp32_small3d(lib):
         assert err.max() <= FP32_TOL, (k, err)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_zero_initialisation_matches_oracle(lib, prec):
+    """xi0 = 0, lambda0 = 0 (the zero warm start of the study): the first step's correction then
+    carries the whole boundary jump."""
+    p = W.small3d(n_robots=6, n_samples=4, horizon=45, seed=17)
+    z = np.zeros_like(p.xi_bar)
+    for k in (1, 40):
+        _say(f"case zero init {prec} k={k}")
+        out = gpu_run(lib, p.cfg, p.xi_bar, p.bvals, k, prec, xi0=z, lam0=z)
+        rx, rl, _ = run_oracle(p.cfg, p.xi_bar, p.bvals, k, xi0=z, lam0=z)
+        if prec == "fp64":
+            assert_fp64(out.xi, rx, "xi")
+            assert_fp64(out.lam, rl, "lambda")
+        else:
+            err = per_sample_rel(out.xi, rx)
+            assert err.max() <= FP32_TOL, (k, err)
+
+
 def test_ragged_batch_equals_separate_calls(lib):
     P = lib
     probs = [W.small3d(n_robots=n, n_samples=s, horizon=30, seed=20 + n) for n, s in ((3, 2), (5, 3), (4, 1))]
