@@ -66,6 +66,10 @@ typedef enum {
                                 also 1-6 workgroups per CU) on 50 (persistent: 30) iterations of this batch and keep the
                                 fastest, also in the JSON-lines cache $SWARMSF_TUNE_CACHE (default
                                 ~/.cache/swarmsf_tune.jsonl) for later processes */
+#define SF_FP_RESIDUAL 32    /* resid_out is [S][3]: the two residual figures, then the fixed-point
+                                residual sum over the iterations, sum_k ||xi^{k+1} - xi^k||^2 +
+                                ||lambda^{k+1} - lambda^k||^2 (the first term of eq. NN_loss); runs
+                                the generic kernel; not with SF_RESID_HISTORY */
 #define SF_PERSISTENT 16     /* run a single-shape batch through the persistent work-queue kernel (a
                                 batch of mixed swarm sizes always uses it on the MFMA path) */
 
@@ -130,15 +134,16 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision,
 
 /* Reverse-mode derivative of sf_project (same batch, precision, iters, xi_bar, bvals
  * and the ckpt it wrote) through the unrolled iterations, eq. (NN_loss) style
- * training of the initialisation.  Given cotangents of xi_out, lam_out and of
- * resid_out[:, 0] (each may be NULL = zero) it writes the gradients with respect to
- * xi0, lam0 and xi_bar (each may be NULL = not wanted).  g_resid is [S].  A batch with a
- * workspace constraint (ws_a > 0) returns SF_EUNSUPPORTED. */
+ * training of the initialisation.  Given cotangents of xi_out, lam_out, of
+ * resid_out[:, 0] (g_resid, [S]) and of the fixed-point residual sum of SF_FP_RESIDUAL
+ * (w_fpr, [S]) -- each may be NULL = zero -- it writes the gradients with respect to
+ * xi0, lam0 and xi_bar (each may be NULL = not wanted).  A batch with a workspace
+ * constraint (ws_a > 0) returns SF_EUNSUPPORTED. */
 sf_status sf_project_backward(sf_handle h, const sf_batch* batch, int32_t precision,
                               const void* xi_bar, const void* bvals, int32_t iters,
                               const void* ckpt, int32_t ckpt_every,
                               const void* g_xi_out, const void* g_lam_out, const void* g_resid,
-                              void* g_xi0, void* g_lam0, void* g_xi_bar, void* stream);
+                              const void* w_fpr, void* g_xi0, void* g_lam0, void* g_xi_bar, void* stream);
 
 /* Constraint violations of coefficient arrays, computed in FP64 on the device at the
  * grid times.  xi is [S, n, D, m] (double for SF_FP64, else float); viol_out is

@@ -12,6 +12,7 @@ SF_GENERIC_KERNEL = 2
 SF_USE_GRAPH = 4
 SF_AUTOTUNE = 8
 SF_PERSISTENT = 16
+SF_FP_RESIDUAL = 32
 PRECISIONS = {"fp64": SF_FP64, "fp32": SF_FP32, "bf16": SF_BF16, "fp16": SF_FP16}
 
 EXPORTED = ["sf_setup", "sf_destroy", "sf_project", "sf_project_backward", "sf_feasibility",
@@ -58,7 +59,7 @@ def lib():
                              vp, c_int32, vp]
     L.sf_project.restype = c_int32
     L.sf_project_backward.argtypes = [vp, POINTER(SfBatch), c_int32, vp, vp, c_int32, vp, c_int32,
-                                      vp, vp, vp, vp, vp, vp, vp]
+                                      vp, vp, vp, vp, vp, vp, vp, vp]
     L.sf_project_backward.restype = c_int32
     L.sf_feasibility.argtypes = [vp, POINTER(SfBatch), c_int32, vp, vp, vp, vp]
     L.sf_feasibility.restype = c_int32

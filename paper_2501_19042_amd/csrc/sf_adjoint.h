@@ -20,11 +20,12 @@ struct AdjointArgs {
   const void* g_xi_out;
   const void* g_lam_out;
   const void* g_resid;
+  const void* w_fpr;            // [S] cotangent of the fixed-point residual sum, or NULL
   void* g_xi0;
   void* g_lam0;
   void* g_xi_bar;
   void* states;                 // scratch: n_items * state_stride elements
-  int64_t state_stride;         // (ckpt_every + 1) * largest n * D * m of the batch
+  int64_t state_stride;         // 2 (ckpt_every + 1) * largest n * D * m of the batch (xi, then lambda)
   int32_t tile;
   size_t lds_bytes;
   hipStream_t stream;

@@ -10,7 +10,9 @@
 //   gY = J_R^T (rho F g_g) per block (J_R the 3x3 Jacobian of the block's residual),
 //   gxi = G_rho u + F^T gY, whose free part is gxi'_free - u + (F^T gY)_free.
 // Pinned coefficients of xi^k are constants for k >= 1, so their cotangent is only formed at
-// k = 0 (G_rho u restricted to them, from Gfx and Rfx).  The forward states inside a
+// k = 0 (G_rho u restricted to them, from Gfx and Rfx).  The fixed-point residual term of
+// eq. (NN_loss), w sum_k ||z^{k+1} - z^k||^2 with z = (xi, lambda), adds 2 w (z^{k+1} - z^k) to
+// the cotangent of z^{k+1} before each reverse step and subtracts it from that of z^k after.  The forward states inside a
 // checkpoint segment are recomputed with the generic iteration and kept in a global scratch.
 #include "sf_generic_impl.h"
 #include "sf_adjoint.h"
@@ -99,7 +101,8 @@ adjoint_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, const
                const WorkItem* __restrict__ items, int n_items, const T* __restrict__ xi_bar,
                const T* __restrict__ bvals, int iters, const T* __restrict__ ckpt, int ckpt_every,
                int64_t ckpt_stride, const T* __restrict__ g_xi_out, const T* __restrict__ g_lam_out,
-               const T* __restrict__ g_resid, T* __restrict__ g_xi0, T* __restrict__ g_lam0,
+               const T* __restrict__ g_resid, const T* __restrict__ w_fpr, T* __restrict__ g_xi0,
+               T* __restrict__ g_lam0,
                T* __restrict__ g_xi_bar, T* __restrict__ states, int64_t state_stride, int TT) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
@@ -124,8 +127,10 @@ adjoint_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, const
     for (int sl = w.first; sl < w.first + w.count; ++sl) {
       const int64_t coef = pr.coef_off + (int64_t)sl * nDm;
       const int64_t sidx = pr.sample_base + sl;
-      T* st = states + (int64_t)it * state_stride;   // one sample per work item
+      T* st = states + (int64_t)it * state_stride;   // one sample per work item: xi states,
+      T* stl = st + (int64_t)(ckpt_every + 1) * nDm;  // then lambda states of a segment
       const T gres = g_resid ? g_resid[sidx] : T(0);
+      const T wf = w_fpr ? w_fpr[sidx] : T(0);
       setup_sample<T>(x, L, xi_bar + coef, bvals + pr.bnd_off, ckpt + coef, ckpt + ckpt_stride + coef);
       for (int q = threadIdx.x; q < nDm; q += blockDim.x) {
         gxi[q] = g_xi_out ? g_xi_out[coef + q] : T(0);
@@ -141,11 +146,15 @@ adjoint_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, const
           L.xi[q] = ckpt[cb + q];
           L.lam[q] = ckpt[cb + ckpt_stride + q];
           st[q] = ckpt[cb + q];
+          stl[q] = ckpt[cb + ckpt_stride + q];
         }
         __syncthreads();
         for (int k = s0; k < s1; ++k) {
           iteration<T>(x, L, TT, k);
-          for (int q = threadIdx.x; q < nDm; q += blockDim.x) st[(int64_t)(k - s0 + 1) * nDm + q] = L.xi[q];
+          for (int q = threadIdx.x; q < nDm; q += blockDim.x) {
+            st[(int64_t)(k - s0 + 1) * nDm + q] = L.xi[q];
+            stl[(int64_t)(k - s0 + 1) * nDm + q] = L.lam[q];
+          }
           __syncthreads();
         }
         // residual term of the loss: r_p = F xi^K - e(F xi^{K-1}) (eq. primal_residual)
@@ -208,6 +217,17 @@ adjoint_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, const
         }
         // reverse sweep over the segment
         for (int k = s1 - 1; k >= s0; --k) {
+          // fixed-point residual term: d/dz^{k+1} of w ||z^{k+1} - z^k||^2
+          auto fpr_term = [&](T sign) {
+            if (wf == T(0)) return;
+            for (int q = threadIdx.x; q < nDm; q += blockDim.x) {
+              const int64_t a1 = (int64_t)(k - s0 + 1) * nDm + q, a0 = (int64_t)(k - s0) * nDm + q;
+              gxi[q] += sign * T(2) * wf * (st[a1] - st[a0]);
+              glam[q] += sign * T(2) * wf * (stl[a1] - stl[a0]);
+            }
+            __syncthreads();
+          };
+          fpr_term(T(1));
           for (int q = threadIdx.x; q < nDm; q += blockDim.x) L.xprev[q] = st[(int64_t)(k - s0) * nDm + q];
           // u = Z S_f Z^T gxi
           for (int q = threadIdx.x; q < D * mf; q += blockDim.x) {
@@ -305,6 +325,7 @@ adjoint_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, const
             for (int q = threadIdx.x; q < nDm; q += blockDim.x) gxi[q] += pend[q];
             __syncthreads();
           }
+          fpr_term(T(-1));   // ... and d/dz^k
         }
       }
       for (int q = threadIdx.x; q < nDm; q += blockDim.x) {
@@ -331,7 +352,8 @@ hipError_t launch_adjoint(const AdjointArgs& a) {
                      static_cast<const T*>(a.tab), a.probs, a.items, a.n_items, static_cast<const T*>(a.xi_bar),
                      static_cast<const T*>(a.bvals), a.iters, static_cast<const T*>(a.ckpt), a.ckpt_every,
                      a.ckpt_stride, static_cast<const T*>(a.g_xi_out), static_cast<const T*>(a.g_lam_out),
-                     static_cast<const T*>(a.g_resid), static_cast<T*>(a.g_xi0), static_cast<T*>(a.g_lam0),
+                     static_cast<const T*>(a.g_resid), static_cast<const T*>(a.w_fpr), static_cast<T*>(a.g_xi0),
+                     static_cast<T*>(a.g_lam0),
                      static_cast<T*>(a.g_xi_bar), static_cast<T*>(a.states), a.state_stride, a.tile);
   return hipGetLastError();
 }

@@ -665,8 +665,11 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
   if (precision < SF_FP64 || precision > SF_FP16) return fail(SF_EINVAL, "unknown precision");
   if (!xi_bar || !bvals || !xi_out) return fail(SF_EINVAL, "xi_bar, bvals and xi_out are required");
   if (iters < 0) return fail(SF_EINVAL, "iters must be >= 0");
-  const int32_t known = SF_RESID_HISTORY | SF_GENERIC_KERNEL | SF_USE_GRAPH | SF_AUTOTUNE | SF_PERSISTENT;
+  const int32_t known = SF_RESID_HISTORY | SF_GENERIC_KERNEL | SF_USE_GRAPH | SF_AUTOTUNE | SF_PERSISTENT | SF_FP_RESIDUAL;
   if (flags & ~known) return fail(SF_EINVAL, "unknown flags");
+  if ((flags & SF_FP_RESIDUAL) && (flags & SF_RESID_HISTORY))
+    return fail(SF_EINVAL, "SF_FP_RESIDUAL and SF_RESID_HISTORY cannot be combined");
+  if ((flags & SF_FP_RESIDUAL) && !resid_out) return fail(SF_EINVAL, "SF_FP_RESIDUAL needs resid_out");
   if (ckpt && ckpt_every < 1) return fail(SF_EINVAL, "ckpt_every must be >= 1 with a checkpoint buffer");
   const size_t elem = precision == SF_FP64 ? sizeof(double) : sizeof(float);
   const void* ptrs[] = {xi_bar, bvals, xi0, lam0, xi_out, lam_out, resid_out, ckpt};
@@ -684,13 +687,14 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
   a.items = p->d_items;
   a.n_items = p->n_items;
   a.xi_bar = xi_bar; a.bvals = bvals; a.xi0 = xi0; a.lam0 = lam0; a.iters = iters;
-  a.xi_out = xi_out; a.lam_out = lam_out; a.resid_out = resid_out; a.flags = flags & SF_RESID_HISTORY;
+  a.xi_out = xi_out; a.lam_out = lam_out; a.resid_out = resid_out;
+  a.flags = flags & (SF_RESID_HISTORY | SF_FP_RESIDUAL);
   a.ckpt = ckpt; a.ckpt_every = ckpt ? ckpt_every : 1; a.ckpt_stride = p->total_coef;
   a.stream = static_cast<hipStream_t>(stream);
 
   // choose the kernel path
   sf::FastPlan* fp = nullptr;
-  if (precision != SF_FP64 && p->fast.ok && !(flags & (SF_RESID_HISTORY | SF_GENERIC_KERNEL))) {
+  if (precision != SF_FP64 && p->fast.ok && !(flags & (SF_RESID_HISTORY | SF_GENERIC_KERNEL | SF_FP_RESIDUAL))) {
     fp = &p->fast;
     if ((flags & SF_PERSISTENT) && !p->fast.batched) {
       if (!p->fast_persistent.ok) {
@@ -770,14 +774,14 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
 sf_status sf_project_backward(sf_handle h, const sf_batch* batch, int32_t precision, const void* xi_bar,
                               const void* bvals, int32_t iters, const void* ckpt, int32_t ckpt_every,
                               const void* g_xi_out, const void* g_lam_out, const void* g_resid,
-                              void* g_xi0, void* g_lam0, void* g_xi_bar, void* stream) {
+                              const void* w_fpr, void* g_xi0, void* g_lam0, void* g_xi_bar, void* stream) {
   g_err.clear();
   if (!h) return fail(SF_EINVAL, "handle is NULL");
   if (precision < SF_FP64 || precision > SF_FP16) return fail(SF_EINVAL, "unknown precision");
   if (!xi_bar || !bvals || !ckpt) return fail(SF_EINVAL, "xi_bar, bvals and ckpt are required");
   if (iters < 0 || ckpt_every < 1) return fail(SF_EINVAL, "iters must be >= 0 and ckpt_every >= 1");
   const size_t elem = precision == SF_FP64 ? sizeof(double) : sizeof(float);
-  const void* ptrs[] = {xi_bar, bvals, ckpt, g_xi_out, g_lam_out, g_resid, g_xi0, g_lam0, g_xi_bar};
+  const void* ptrs[] = {xi_bar, bvals, ckpt, g_xi_out, g_lam_out, g_resid, w_fpr, g_xi0, g_lam0, g_xi_bar};
   for (const void* q : ptrs)
     if (q && !aligned(q, elem)) return fail(SF_EINVAL, "misaligned array");
   std::lock_guard<std::mutex> lock(h->mu);
@@ -793,7 +797,7 @@ sf_status sf_project_backward(sf_handle h, const sf_batch* batch, int32_t precis
     max_ndm = std::max<int64_t>(max_ndm, (int64_t)c.n * c.D * c.m);
   }
   sf::AdjointArgs a{};
-  a.state_stride = (int64_t)(ckpt_every + 1) * max_ndm;
+  a.state_stride = (int64_t)2 * (ckpt_every + 1) * max_ndm;   // xi and lambda states of a segment
   const size_t need = (size_t)p->n_items * a.state_stride * elem;
   if (need > h->scratch_bytes) {
     if (h->scratch) (void)hipFree(h->scratch);
@@ -809,7 +813,7 @@ sf_status sf_project_backward(sf_handle h, const sf_batch* batch, int32_t precis
   a.n_items = p->n_items;
   a.xi_bar = xi_bar; a.bvals = bvals; a.iters = iters; a.ckpt = ckpt; a.ckpt_every = ckpt_every;
   a.ckpt_stride = p->total_coef;
-  a.g_xi_out = g_xi_out; a.g_lam_out = g_lam_out; a.g_resid = g_resid;
+  a.g_xi_out = g_xi_out; a.g_lam_out = g_lam_out; a.g_resid = g_resid; a.w_fpr = w_fpr;
   a.g_xi0 = g_xi0; a.g_lam0 = g_lam0; a.g_xi_bar = g_xi_bar;
   a.states = h->scratch;
   a.stream = static_cast<hipStream_t>(stream);

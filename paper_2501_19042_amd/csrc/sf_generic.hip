@@ -35,6 +35,8 @@ generic_project_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ ta
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   const bool history = (flags & 1) != 0;
+  const bool fpr = (flags & 32) != 0;   // resid_out [S][3] with the fixed-point residual sum
+  const int rw = fpr ? 3 : 2;
 
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const WorkItem w = items[it];
@@ -47,6 +49,7 @@ generic_project_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ ta
       const int64_t sidx = pr.sample_base + sl;
       setup_sample<T>(x, L, xi_bar + coef, bvals + pr.bnd_off, xi0 ? xi0 + coef : nullptr,
                       lam0 ? lam0 + coef : nullptr);
+      T fsum = T(0);   // this thread's share of the fixed-point residual sum
       for (int k = 0; k < iters; ++k) {
         if (ckpt && (k % ckpt_every) == 0) {
           const int64_t base = (int64_t)(k / ckpt_every) * 2 * ckpt_stride + coef;
@@ -55,9 +58,18 @@ generic_project_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ ta
             ckpt[base + ckpt_stride + q] = L.lam[q];
           }
         }
-        if (history || (resid_out && k == iters - 1))
+        if (history || fpr || (resid_out && k == iters - 1))
           for (int q = threadIdx.x; q < nDm; q += blockDim.x) L.xprev[q] = L.xi[q];
         iteration<T>(x, L, TT, k);
+        if (fpr) {
+          // ||xi^{k+1} - xi^k||^2 + ||lambda^{k+1} - lambda^k||^2, with lambda^{k+1} - lambda^k = -g
+          for (int q = threadIdx.x; q < nDm; q += blockDim.x) {
+            const T d = L.xi[q] - L.xprev[q];
+            fsum = fma(d, d, fsum);
+            fsum = fma(L.g[q], L.g[q], fsum);
+          }
+          __syncthreads();
+        }
         if (history && resid_out) {
           T ss, mx;
           residual_pass<T>(x.c, x.basis, L, TT, ss, mx);
@@ -70,9 +82,14 @@ generic_project_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ ta
       if (resid_out && !history) {
         T ss = T(0), mx = T(0);
         if (iters > 0) residual_pass<T>(x.c, x.basis, L, TT, ss, mx);
+        if (fpr) {
+          T unused = T(0);
+          block_reduce_sum_max<T>(L.red, fsum, unused);
+        }
         if (threadIdx.x == 0) {
-          resid_out[sidx * 2 + 0] = ss;
-          resid_out[sidx * 2 + 1] = mx;
+          resid_out[sidx * rw + 0] = ss;
+          resid_out[sidx * rw + 1] = mx;
+          if (fpr) resid_out[sidx * rw + 2] = fsum;
         }
       }
       for (int q = threadIdx.x; q < nDm; q += blockDim.x) {

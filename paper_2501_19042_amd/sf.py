@@ -97,7 +97,8 @@ class SafetyFilter:
                 precision: str = "fp32", xi0: Optional[torch.Tensor] = None, lam0: Optional[torch.Tensor] = None,
                 want_lam: bool = True, want_resid: bool = True, history: bool = False,
                 ckpt_every: int = 0, generic: bool = False, graph: bool = False, autotune: bool = False,
-                persistent: bool = False, out: Optional[ProjectResult] = None, stream=None) -> ProjectResult:
+                persistent: bool = False, fp_residual: bool = False, out: Optional[ProjectResult] = None,
+                stream=None) -> ProjectResult:
         prec = N.PRECISIONS[precision]
         dtype = torch.float64 if prec == N.SF_FP64 else torch.float32
         batch = self._batch(batch, xi_bar)
@@ -111,14 +112,15 @@ class SafetyFilter:
             lam_out = torch.empty_like(xi_bar) if want_lam else None
             resid = None
             if want_resid:
-                resid = torch.empty((S, iters, 2) if history else (S, 2), dtype=dtype, device=self.device)
+                resid = torch.empty((S, iters, 2) if history else (S, 3 if fp_residual else 2), dtype=dtype,
+                                    device=self.device)
             ckpt = None
             if ckpt_every:
                 nck = max(1, math.ceil(iters / ckpt_every))
                 ckpt = torch.empty((nck, 2, coef), dtype=dtype, device=self.device)
         flags = ((N.SF_RESID_HISTORY if history else 0) | (N.SF_GENERIC_KERNEL if generic else 0)
                  | (N.SF_USE_GRAPH if graph else 0) | (N.SF_AUTOTUNE if autotune else 0)
-                 | (N.SF_PERSISTENT if persistent else 0))
+                 | (N.SF_PERSISTENT if persistent else 0) | (N.SF_FP_RESIDUAL if fp_residual else 0))
         N.check(N.lib().sf_project(self._h, ctypes.byref(batch.c), prec, _ptr(xi_bar), _ptr(bvals), _ptr(xi0),
                                    _ptr(lam0), int(iters), _ptr(xi_out), _ptr(lam_out), _ptr(resid), flags,
                                    _ptr(ckpt), int(ckpt_every), _stream_ptr(stream)))
@@ -126,18 +128,19 @@ class SafetyFilter:
 
     def project_backward(self, xi_bar, bvals, iters, ckpt, ckpt_every, g_xi_out=None, g_lam_out=None,
                          g_resid=None, batch: Optional[Batch] = None, precision: str = "fp32",
-                         want=("xi0", "lam0", "xi_bar"), stream=None):
+                         want=("xi0", "lam0", "xi_bar"), w_fpr=None, stream=None):
         prec = N.PRECISIONS[precision]
         dtype = torch.float64 if prec == N.SF_FP64 else torch.float32
         batch = self._batch(batch, xi_bar)
         S, coef, bnd = self.sizes(batch)
         for t, nm, ne in ((xi_bar, "xi_bar", coef), (bvals, "bvals", bnd), (g_xi_out, "g_xi_out", coef),
-                          (g_lam_out, "g_lam_out", coef), (g_resid, "g_resid", S)):
+                          (g_lam_out, "g_lam_out", coef), (g_resid, "g_resid", S), (w_fpr, "w_fpr", S)):
             self._check(t, nm, dtype, ne)
         out = {k: (torch.empty_like(xi_bar) if k in want else None) for k in ("xi0", "lam0", "xi_bar")}
         N.check(N.lib().sf_project_backward(self._h, ctypes.byref(batch.c), prec, _ptr(xi_bar), _ptr(bvals),
                                             int(iters), _ptr(ckpt), int(ckpt_every), _ptr(g_xi_out),
-                                            _ptr(g_lam_out), _ptr(g_resid), _ptr(out["xi0"]), _ptr(out["lam0"]),
+                                            _ptr(g_lam_out), _ptr(g_resid), _ptr(w_fpr), _ptr(out["xi0"]),
+                                            _ptr(out["lam0"]),
                                             _ptr(out["xi_bar"]), _stream_ptr(stream)))
         return out
 
@@ -230,26 +233,28 @@ class _SFProject(torch.autograd.Function):
     @staticmethod
     def forward(ctx, xi0, lam0, xi_bar, bvals, sf, batch, iters, ckpt_every, precision):
         out = sf.project(xi_bar.detach(), bvals.detach(), iters, batch=batch, precision=precision,
-                         xi0=xi0.detach(), lam0=lam0.detach(), ckpt_every=ckpt_every, generic=True)
+                         xi0=xi0.detach(), lam0=lam0.detach(), ckpt_every=ckpt_every, generic=True,
+                         fp_residual=True)
         ctx.save_for_backward(xi_bar.detach(), bvals.detach(), out.ckpt)
         ctx.cfg = (sf, batch, iters, ckpt_every, precision)
-        return out.xi, out.lam, out.resid[:, 0].contiguous()
+        return out.xi, out.lam, out.resid[:, 0].contiguous(), out.resid[:, 2].contiguous()
 
     @staticmethod
-    def backward(ctx, g_xi, g_lam, g_res):
+    def backward(ctx, g_xi, g_lam, g_res, g_fpr):
         xi_bar, bvals, ckpt = ctx.saved_tensors
         sf, batch, iters, ckpt_every, precision = ctx.cfg
         c = lambda t: None if t is None else t.contiguous()
         g = sf.project_backward(xi_bar, bvals, iters, ckpt, ckpt_every, g_xi_out=c(g_xi), g_lam_out=c(g_lam),
-                                g_resid=c(g_res), batch=batch, precision=precision)
+                                g_resid=c(g_res), w_fpr=c(g_fpr), batch=batch, precision=precision)
         return g["xi0"], g["lam0"], g["xi_bar"], None, None, None, None, None, None
 
 
 def project_differentiable(sf: SafetyFilter, xi_bar: torch.Tensor, bvals: torch.Tensor, iters: int,
                            xi0: Optional[torch.Tensor] = None, lam0: Optional[torch.Tensor] = None,
                            ckpt_every: int = 10, batch: Optional[Batch] = None, precision: str = "fp32"):
-    """Differentiable SF: returns (xi_K, lambda_K, ||r_p^K||^2 per sample); gradients flow to
-    xi0, lam0 and xi_bar through the adjoint kernel.  xi0 = None starts from xi_bar (its
+    """Differentiable SF: returns (xi_K, lambda_K, ||r_p^K||^2 per sample, and the fixed-point
+    residual sum_k ||z^{k+1} - z^k||^2 per sample, the first term of eq. (NN_loss)); gradients
+    flow to xi0, lam0 and xi_bar through the adjoint kernel.  xi0 = None starts from xi_bar (its
     gradient then adds to xi_bar's), lam0 = None starts from zero."""
     if xi0 is None:
         xi0 = xi_bar

@@ -10,6 +10,10 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 
+def _say(msg):
+    print(msg, flush=True)
+
+
 @pytest.fixture(scope="module")
 def P():
     import paper_2501_19042_amd as P
@@ -55,7 +59,7 @@ def gpu_grads(P, cfg, xi_bar, b, lam0, iters, ce, precision):
     l0 = torch.tensor(lam0, dtype=dt, device="cuda").requires_grad_(True)
     xbr = xb.clone().requires_grad_(True)
     bv = torch.tensor(b, dtype=dt, device="cuda")
-    xk, lk, res = P.project_differentiable(sf, xbr, bv, iters, xi0=x0, lam0=l0, ckpt_every=ce, precision=precision)
+    xk, lk, res, _ = P.project_differentiable(sf, xbr, bv, iters, xi0=x0, lam0=l0, ckpt_every=ce, precision=precision)
     L = loss_fn(xk, xb, res)
     gx0, gl0, gxb = torch.autograd.grad(L, (x0, l0, xbr))
     torch.cuda.synchronize()
@@ -119,7 +123,7 @@ def test_adjoint_diff16_full_size(P):
     lam0 = torch.zeros_like(xb)
     x0 = xb.clone().requires_grad_(True)
     l0 = lam0.clone().requires_grad_(True)
-    xk, lk, res = P.project_differentiable(sf, xb, bv, wl.iters, xi0=x0, lam0=l0, ckpt_every=wl.ckpt_every)
+    xk, lk, res, _ = P.project_differentiable(sf, xb, bv, wl.iters, xi0=x0, lam0=l0, ckpt_every=wl.ckpt_every)
     L = loss_fn(xk, xb, res)
     gx0, gl0 = torch.autograd.grad(L, (x0, l0))
     assert torch.isfinite(gx0).all() and torch.isfinite(gl0).all()
@@ -142,3 +146,39 @@ def test_adjoint_diff16_full_size(P):
     og = oracle_grads(p.cfg, p.xi_bar[idx], p.bvals, np.zeros_like(p.xi_bar[idx]), wl.iters)
     for nm, a, r in zip(("xi0", "lam0"), (gx0[idx].cpu().double(), gl0[idx].cpu().double()), og[:2]):
         assert rel_err(a, r) <= 5e-3, (nm, rel_err(a, r))
+
+
+@pytest.mark.parametrize("iters,ce", [(12, 5), (7, 10)])
+def test_fixed_point_residual_term_matches_oracle(P, iters, ce):
+    """The first term of eq. (NN_loss), w sum_k ||z^{k+1} - z^k||^2 with z = (xi, lambda): its
+    value (SF_FP_RESIDUAL) and its gradients through the adjoint, against autograd through the
+    oracle's iterations taken one at a time (the oracle solves the exact KKT system each step, so
+    chained single steps equal one longer run)."""
+    cfg, xi_bar, b, rng = problem(seed=12)
+    lam0 = rng.normal(size=xi_bar.shape) * 0.1
+    w = 0.7
+    s = O.build_system(cfg)
+    xb = torch.tensor(xi_bar)
+    x0 = torch.tensor(xi_bar + rng.normal(size=xi_bar.shape) * 0.05, requires_grad=True)
+    l0 = torch.tensor(lam0, requires_grad=True)
+    xi, lam = x0, l0
+    fsum = torch.zeros(xi_bar.shape[0], dtype=torch.float64)
+    for _ in range(iters):
+        xn, ln, _ = O.sf_project(s, xb, torch.tensor(b), 1, xi0=xi, lam0=lam)
+        fsum = fsum + ((xn - xi) ** 2).sum((1, 2, 3)) + ((ln - lam) ** 2).sum((1, 2, 3))
+        xi, lam = xn, ln
+    L = w * fsum.sum() + ((xi - xb) ** 2).sum()
+    gx0, gl0 = torch.autograd.grad(L, (x0, l0))
+    _say(f"case nn_loss fixed-point term fp64 iters={iters} ckpt_every={ce}")
+    sf = P.SafetyFilter([cfg])
+    xbd = xb.cuda()
+    x0d = x0.detach().cuda().requires_grad_(True)
+    l0d = l0.detach().cuda().requires_grad_(True)
+    xk, _, _, fpr = P.project_differentiable(sf, xbd, torch.tensor(b).cuda(), iters, xi0=x0d, lam0=l0d,
+                                             ckpt_every=ce, precision="fp64")
+    assert torch.allclose(fpr.cpu(), fsum.detach(), rtol=1e-9, atol=1e-12), (fpr, fsum)
+    Lg = w * fpr.sum() + ((xk - xbd) ** 2).sum()
+    g0, g1 = torch.autograd.grad(Lg, (x0d, l0d))
+    torch.cuda.synchronize()
+    assert rel_err(g0.cpu().double(), gx0) <= 1e-8
+    assert rel_err(g1.cpu().double(), gl0) <= 1e-8
