@@ -379,7 +379,7 @@ def main():
                     help="only run 3 device copies of 256 MiB (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus above 1 is not supported "
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus above 1 is not supported "
                                    "(samples are independent: a multi-GPU run would give each GPU a cost-balanced slice of the problem table)"}))
         sys.exit(2)
     import torch
