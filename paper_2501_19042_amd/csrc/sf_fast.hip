@@ -97,7 +97,7 @@ constexpr int kQPCols = 16;              // QP matrix row in LDS: both halves, e
 constexpr int kBoxRow = 12;
 constexpr int kHBRow = 20;
 struct FastLds {
-  int xi, lam, xb, xprev, dbar, corr, pairs, vmx, amx, dxi, cmx, qp, hb, tiles, per_wave, total;
+  int xi, lam, xb, xprev, dbar, corr, pairs, vmx, amx, wmx, dxi, cmx, qp, hb, tiles, per_wave, total;
   int xt, ct, bb, plist;   // offsets inside one wave's tile region
 };
 
@@ -133,6 +133,7 @@ __host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W, 
   p.per_wave = (pw + 3) & ~3;
   p.tiles = o;
   o += W * p.per_wave;
+  p.wmx = o; o += c.ws_on ? W * nr : 0;    // per wave and robot: max ||M_w^{-1} (p - p_w)||^2 (workspace)
   p.total = o;
   return p;
 }
@@ -292,6 +293,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
     float* s_amx = smem + L.amx;
     float* s_dxi = smem + L.dxi;
     float* s_cmx = smem + L.cmx;
+    float* s_wmx = smem + L.wmx;
     // 16-bit hi/lo split of xi in the S1 B-operand layout, kept current by whoever writes xi
     typedef typename Half<MP == 0 ? 1 : MP>::E HE;
     HE* shb = reinterpret_cast<HE*>(smem + L.hb);
@@ -393,6 +395,10 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
       // the last evaluation and accumulated bound on the drift since then
       float mv = -1.0f, dv = 0.0f, ma = -1.0f, da = 0.0f;
       int prev_eval = 0;
+      // the same for the workspace rows, as one slack: 1 - max ||M_w^{-1} (p - p_w)|| at the last
+      // evaluation minus the scaled drift bounds of the positions since then
+      float wsl = -1.0f;
+      int ws_prev = 0;
       // pair lists: accumulated bound on the position change of robot `lane` per axis since the lists
       // were built (a position is a convex combination of its coefficients, so it moves by at most
       // the largest change of a coefficient)
@@ -450,6 +456,16 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             px_ += d0;
             py_ += d1;
             pz_ += d2;
+            if constexpr (WS) {
+              if (ws_prev) {
+                float mx = 0.0f;
+#pragma unroll
+                for (int ww = 0; ww < W; ++ww) mx = fmaxf(mx, s_wmx[ww * NR + lane]);
+                wsl = 1.0f - __builtin_amdgcn_sqrtf(mx);
+              }
+              // ||M_w^{-1} (sum of steps)|| <= sum of ||M_w^{-1} step|| (triangle inequality)
+              wsl -= __builtin_amdgcn_sqrtf((d0 * d0 + d1 * d1) * wia2 + d2 * d2 * wib2);
+            }
           }
           dv += Lv * dn;
           da += La * dn;
@@ -458,6 +474,17 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           if (k >= 2) eval_flags = (ballot(fv) != 0 ? 1 : 0) | (ballot(fa) != 0 ? 2 : 0);
         }
         prev_eval = eval_flags;
+        // Workspace rows: a position moves per step by at most the largest coefficient change
+        // per axis, so while max ||M_w^{-1} (p - p_w)|| at the last evaluation plus the summed
+        // scaled drift stays below 1 (1e-4 slack) every workspace residual is exactly zero and the
+        // rows are skipped.
+        bool ws_eval = false;
+        if constexpr (WS) {
+          if (c.ws_on) {
+            ws_eval = k < 2 || ballot(lane < n && wsl <= 1e-4f) != 0;
+            ws_prev = ws_eval;
+          }
+        }
         // Rebuild the pair lists when some robot may have moved by more than the margin they were
         // built with (and in iterations 0 and 1, where the pinned coefficients jump).
         const bool rebuild = k < 2 || ballot(lane < n && (px_ > skx || py_ > skx || pz_ > skz)) != 0;
@@ -536,8 +563,11 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
 #pragma unroll
           for (int d = 0; d < 3; ++d) gacc[rr][d] = f4{0.0f, 0.0f, 0.0f, 0.0f};
         float vm[2][R];           // max ||v||^2, ||a||^2 of robot col over this wave's tiles
+        float wsm[WS ? R : 1];    // max ||M_w^{-1} (p - p_w)||^2 of robot col over this wave's tiles
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) vm[0][rr] = vm[1][rr] = 0.0f;
+#pragma unroll
+        for (int rr = 0; rr < (WS ? R : 1); ++rr) wsm[rr] = 0.0f;
         // position operands of the wave's first tile; each tile prefetches those of its next one
         float4 pa = {0.0f, 0.0f, 0.0f, 0.0f}, pb = {0.0f, 0.0f, 0.0f, 0.0f};
         uint4 pu1 = {0u, 0u, 0u, 0u}, pu2 = {0u, 0u, 0u, 0u};
@@ -605,14 +635,16 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             // workspace rows (F_w of eq. f_e) on the same positions: residual (p - p_w) max(0,
             // 1 - 1/||M_w^{-1} (p - p_w)||), scaled by rho_w / rho_c so that it joins the collision
             // residuals in the accumulator (zero until now) and their S4 product
-            if (WS && c.ws_on) {
+            if (WS && ws_eval) {
               bool wnz = false;
 #pragma unroll
-              for (int rr = 0; rr < R; ++rr)
+              for (int rr = 0; rr < R; ++rr) {
+                float mx = 0.0f;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                   const float qx = Y[rr][0][r] - wcx, qy = Y[rr][1][r] - wcy, qz = Y[rr][2][r] - wcz;
                   const float s2 = (qx * qx + qy * qy) * wia2 + qz * qz * wib2;
+                  mx = fmaxf(mx, s2);
                   // (s2 > 1 is a normal number, so the bare hardware rsqrt serves)
                   const float f = (16 * rr + col < n && s2 > 1.0f) ? wsc * (1.0f - __builtin_amdgcn_rsqf(s2)) : 0.0f;
                   Y[rr][0][r] = f * qx;
@@ -620,6 +652,8 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                   Y[rr][2][r] = f * qz;
                   wnz |= f != 0.0f;
                 }
+                wsm[WS ? rr : 0] = fmaxf(wsm[WS ? rr : 0], grp_max(mx));
+              }
               if (ballot(wnz) != 0) {
                 ws_nz = true;
 #pragma unroll
@@ -766,6 +800,8 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             for (int rr = 0; rr < R; ++rr) {
               if (eval_flags & 1) s_vmx[wave * NR + 16 * rr + col] = vm[0][rr];
               if (eval_flags & 2) s_amx[wave * NR + 16 * rr + col] = vm[1][rr];
+              if constexpr (WS)
+                if (ws_eval) s_wmx[wave * NR + 16 * rr + col] = wsm[rr];
             }
           }
         }
