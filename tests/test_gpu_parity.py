@@ -280,3 +280,28 @@ def test_errors_surface_as_exceptions(lib):
     from paper_2501_19042_amd._native import SfError
     with pytest.raises(SfError):
         sf.project_backward(xb, bv, 5, None, 0)
+
+
+def test_flag_combinations_are_checked(lib):
+    """SF_FP_RESIDUAL needs resid_out and excludes SF_RESID_HISTORY; unknown flags are refused; the
+    fixed-point residual column matches across precisions of the generic kernel."""
+    import ctypes
+    from paper_2501_19042_amd import _native as N
+    P = lib
+    p = W.small3d(n_robots=3, n_samples=2, horizon=12)
+    sf = P.SafetyFilter([p.cfg])
+    xb = torch.as_tensor(p.xi_bar, dtype=torch.float64).cuda()
+    bv = torch.as_tensor(p.bvals, dtype=torch.float64).cuda()
+    out = torch.empty_like(xb)
+    res = torch.empty((2, 3), dtype=torch.float64).cuda()
+    batch = sf._batch(None, xb)
+    call = lambda flags, r: N.lib().sf_project(sf._h, ctypes.byref(batch.c), N.SF_FP64, xb.data_ptr(), bv.data_ptr(),
+                                               None, None, 5, out.data_ptr(), None, r, flags, None, 0, None)
+    assert call(N.SF_FP_RESIDUAL, None) == N.SF_EINVAL
+    assert call(N.SF_FP_RESIDUAL | N.SF_RESID_HISTORY, res.data_ptr()) == N.SF_EINVAL
+    assert call(1 << 20, res.data_ptr()) == N.SF_EINVAL
+    assert call(N.SF_FP_RESIDUAL, res.data_ptr()) == N.SF_OK
+    torch.cuda.synchronize()
+    r32 = sf.project(xb.float(), bv.float(), 5, precision="fp32", fp_residual=True).resid.cpu().double()
+    assert torch.allclose(res.cpu()[:, 2], r32[:, 2], rtol=1e-4)
+    assert (res.cpu()[:, 2] > 0).all()
