@@ -89,7 +89,8 @@ def test_factor_table_matches_dense_kkt(cfg):
 @pytest.mark.parametrize("field,value,code", [
     ("n_robots", 1, N.SF_EINVAL), ("dims", 4, N.SF_EINVAL), ("degree", 4, N.SF_EINVAL),
     ("horizon", 5, N.SF_EINVAL), ("t_final", 0.0, N.SF_EINVAL), ("safety_a", 0.0, N.SF_EINVAL),
-    ("rho_coll", 0.0, N.SF_EINVAL), ("n_robots", 65, N.SF_EUNSUPPORTED),
+    ("rho_coll", 0.0, N.SF_EINVAL), ("n_robots", 65, N.SF_EUNSUPPORTED), ("degree", 31, N.SF_EUNSUPPORTED),
+    ("horizon", 4097, N.SF_EUNSUPPORTED),
 ])
 def test_factor_table_rejects_bad_configs(field, value, code):
     c = N.make_config(W.cfg_swarm(16))
