@@ -182,3 +182,24 @@ def test_fixed_point_residual_term_matches_oracle(P, iters, ce):
     torch.cuda.synchronize()
     assert rel_err(g0.cpu().double(), gx0) <= 1e-8
     assert rel_err(g1.cpu().double(), gl0) <= 1e-8
+
+
+@pytest.mark.parametrize("precision,n,tol", [("fp64", 40, 1e-8), ("fp32", 64, 2e-3)])
+def test_adjoint_at_its_size_limits(P, precision, n, tol):
+    """The most robots the adjoint's LDS plan takes at degree 10 (FP64: 40 robots in 150 KB; FP32:
+    64 robots in 118 KB), both with a one-step time tile, against autograd through the oracle."""
+    cfg, xi, b, rng = problem(n=n, S=1, H=40, degree=10, seed=30 + n, box=4.0)
+    lam0 = rng.normal(size=xi.shape) * 0.1
+    og = oracle_grads(cfg, xi, b, lam0, 6)
+    _say(f"case adjoint limits {precision} n={n} degree=10 H=40 iters=6 ckpt_every=4")
+    gg = gpu_grads(P, cfg, xi, b, lam0, 6, 4, precision)
+    for nm, a, r in zip(("xi0", "lam0", "xi_bar"), gg[:3], og):
+        assert rel_err(a, r) <= tol, (nm, rel_err(a, r))
+
+
+def test_adjoint_refuses_shapes_past_its_lds_bound(P):
+    from paper_2501_19042_amd import _native as N
+    cfg, xi, b, rng = problem(n=44, S=1, H=40, degree=10, seed=74, box=4.0)
+    _say("case adjoint limits refusal fp64 n=44")
+    with pytest.raises(N.SfError):
+        gpu_grads(P, cfg, xi, b, np.zeros_like(xi), 4, 4, "fp64")
