@@ -129,3 +129,37 @@ def test_reverse_mode_optional_outputs(P):
     assert torch.allclose(gb.cpu(), bo.grad, atol=1e-12, rtol=1e-12)
     with pytest.raises(N.SfError):
         N.check(N.lib().sf_qp_equality_backward(sf._h, ctypes.byref(batch.c), N.SF_FP64, None, None, None, None))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_largest_shape(P, prec):
+    """64 robots, degree 30 (31 coefficients, an odd row length), 20 samples: forward and reverse
+    mode against the oracle."""
+    p = W.small3d(n_robots=64, n_samples=20, degree=30, horizon=45, seed=90,
+                  box=((-4.0, -4.0, -1.0), (4.0, 4.0, 1.0)))
+    rng = np.random.default_rng(91)
+    xi = p.xi_bar + rng.normal(size=p.xi_bar.shape) * 0.3
+    wts = rng.normal(size=xi.shape)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    sf = P.SafetyFilter([p.cfg])
+    x = torch.as_tensor(xi, dtype=dt).cuda().requires_grad_(True)
+    b = torch.as_tensor(p.bvals, dtype=dt).cuda().requires_grad_(True)
+    _say(f"case qp_equality largest shape {prec} n=64 degree=30 S=20")
+    y = P.qp_equality_differentiable(sf, x, b, precision=prec)
+    (y * torch.as_tensor(wts, dtype=dt).cuda()).sum().backward()
+    torch.cuda.synchronize()
+    xo = torch.as_tensor(xi).requires_grad_(True)
+    bo = torch.as_tensor(p.bvals).requires_grad_(True)
+    ref = O.qp_equality(O.build_system(p.cfg), xo, bo)
+    (ref * torch.as_tensor(wts)).sum().backward()
+    got = y.detach().cpu().double()
+    ref = ref.detach()
+    if prec == "fp64":
+        assert ((got - ref).abs() / (1 + ref.abs())).max().item() <= 1e-12
+    else:
+        rel = (got - ref).abs().reshape(20, -1).amax(1) / ref.abs().reshape(20, -1).amax(1)
+        assert rel.max().item() <= 1e-6, rel
+    assert torch.equal(y.detach()[..., 3:-3].cpu(), x.detach()[..., 3:-3].cpu())
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    assert ((x.grad.cpu().double() - xo.grad).abs().max() / xo.grad.abs().max()).item() <= tol
+    assert ((b.grad.cpu().double() - bo.grad).abs().max() / bo.grad.abs().max()).item() <= tol
