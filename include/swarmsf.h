@@ -127,8 +127,9 @@ void sf_destroy(sf_handle h);
  *          sf_project_backward.
  * Aliasing: outputs must not overlap inputs or each other.
  * Kernel choice is per call: SF_FP32 runs on the MFMA kernel when every problem of the batch
- * has a shape it covers (see SF_FP16) that fits its LDS plan, and no SF_RESID_HISTORY, SF_GENERIC_KERNEL or
- * SF_FP_RESIDUAL is set; otherwise the whole batch runs on the generic kernel. */
+ * has a shape it covers (see SF_FP16) that fits its LDS plan, and none of SF_RESID_HISTORY,
+ * SF_GENERIC_KERNEL or SF_FP_RESIDUAL is set; otherwise the whole batch runs on the generic
+ * kernel. */
 sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision,
                      const void* xi_bar, const void* bvals,
                      const void* xi0, const void* lam0, int32_t iters,
