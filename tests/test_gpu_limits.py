@@ -112,3 +112,27 @@ def test_shapes_past_the_lds_bound_are_refused(P, precision, n, degree):
     _say(f"case limits refusal {precision} n={n} degree={degree}")
     with pytest.raises(N.SfError):
         gpu_run(P, p, 2, precision)
+
+
+def test_batch_mixing_covered_and_uncovered_shapes(P):
+    """One FP32 call over a 64-robot problem (outside the MFMA kernel's shapes) and a 16-robot
+    problem (inside them): the whole batch runs on the generic kernel with the one-step time tile
+    the larger problem needs, and each problem matches the oracle."""
+    probs = [problem(64, 10, 60, 2), problem(16, 10, 100, 3)]
+    sf = P.SafetyFilter([p.cfg for p in probs])
+    batch = P.Batch([(i, p.xi_bar.shape[0]) for i, p in enumerate(probs)])
+    xb = torch.cat([torch.as_tensor(p.xi_bar, dtype=torch.float32).reshape(-1) for p in probs]).cuda()
+    bv = torch.cat([torch.as_tensor(p.bvals, dtype=torch.float32).reshape(-1) for p in probs]).cuda()
+    iters = 6
+    _say(f"case limits mixed batch fp32 n=64+16 iters={iters}")
+    out = sf.project(xb, bv, iters, batch=batch, precision="fp32")
+    torch.cuda.synchronize()
+    o = 0
+    for p in probs:
+        S = p.xi_bar.shape[0]
+        rx, _, _ = oracle_run(p, iters)
+        g = out.xi[o:o + p.xi_bar.size].cpu().double().reshape(S, -1)
+        r = rx.reshape(S, -1)
+        e = ((g - r).abs().amax(1) / r.abs().amax(1)).numpy()
+        assert e.max() <= FP32_TOL, e
+        o += p.xi_bar.size
