@@ -621,6 +621,55 @@ def test_two_robot_head_on_against_slsqp():
     assert np.sqrt(np.sum((X[0] - X[1]) ** 2, axis=0)).min() >= cfg.safety_a - 1e-3
 
 
+def test_three_robot_crossing_against_slsqp():
+    """Three robots in 2D on a unit circle crossing through its centre to the antipodes: the SF
+    output is feasible, and its cost is no lower than the local optimum scipy's SLSQP reaches from
+    it (and from xi_bar: the same optimum) and within a small factor of it (one-sided: the SF
+    converges to a feasible point near xi_bar, not to the minimiser of eq. sf_form)."""
+    n = 3
+    cfg = small_cfg(n=n, D=2, degree=7, H=16, T=4.0, vmax=3.0, amax=6.0)
+    th = 2 * np.pi * np.arange(n) / n + 0.1
+    st = np.stack([np.cos(th), np.sin(th)], 1)
+    gl = -st
+    rng = np.random.default_rng(17)
+    xi_bar = W.straight_line_coeffs(st, gl, cfg.degree)[None] + rng.normal(size=(1, n, 2, 8)) * 0.05
+    b = W.boundary_values(st, gl)
+    s = O.build_system(cfg)
+    out, _, _ = O.sf_project(s, torch.tensor(xi_bar), torch.tensor(b), 3000)
+    sf = out.numpy()[0].reshape(-1)
+    P, Pd, Pdd = s.P.numpy(), s.Pd.numpy(), s.Pdd.numpy()
+    A1 = np.stack([P[0], Pd[0], Pdd[0], P[-1], Pd[-1], Pdd[-1]])
+
+    def cost(z):
+        return 0.5 * np.sum((z - xi_bar[0].reshape(-1)) ** 2)
+
+    def eq(z):
+        c = z.reshape(n, 2, 8)
+        return np.concatenate([A1 @ c[i, d] - b[i, d] for i in range(n) for d in range(2)])
+
+    def ineq(z):
+        c = z.reshape(n, 2, 8)
+        X = np.einsum("hk,idk->idh", P, c)
+        V = np.einsum("hk,idk->idh", Pd, c)
+        A = np.einsum("hk,idk->idh", Pdd, c)
+        pairs = [np.sum((X[i] - X[j]) ** 2, axis=0) - cfg.safety_a ** 2 for i in range(n) for j in range(i + 1, n)]
+        return np.concatenate(pairs + [cfg.vmax ** 2 - np.sum(V ** 2, axis=1).ravel(),
+                                       cfg.amax ** 2 - np.sum(A ** 2, axis=1).ravel()])
+    assert np.abs(eq(sf)).max() < 1e-10
+    assert ineq(sf).min() > -1e-3                       # SF output feasible
+    cons = [dict(type="eq", fun=eq), dict(type="ineq", fun=ineq)]
+    opts = dict(maxiter=500, ftol=1e-14)
+    res = scipy.optimize.minimize(cost, sf, method="SLSQP", constraints=cons, options=opts)
+    res_bar = scipy.optimize.minimize(cost, xi_bar[0].reshape(-1), method="SLSQP", constraints=cons, options=opts)
+    assert res.success and res_bar.success
+    assert abs(res.fun - res_bar.fun) <= 1e-8 * res.fun
+    assert cost(sf) >= res.fun - 1e-9
+    assert cost(sf) <= 3.0 * res.fun + 1e-6
+    X = np.einsum("hk,idk->idh", P, out.numpy()[0])
+    dmin = min(np.sqrt(np.sum((X[i] - X[j]) ** 2, axis=0)).min() for i in range(n) for j in range(i + 1, n))
+    assert dmin >= cfg.safety_a - 1e-3
+
+
 # --------------------------------------------------------------------------
 # autograd through the oracle (reference gradients) against central differences
 # --------------------------------------------------------------------------
