@@ -38,25 +38,28 @@ DTYPES = {"fp64": "f64", "fp32": "f32", "bf16": "f32 state, bf16 MFMA basis prod
 
 
 def flops_split(cfg):
-    """Algorithmic flops of one iteration for one sample (multiply-add = 2), split into the dense
-    contractions (basis evaluation 6nDHm, back-projection to the free coefficients 6nDHm_f, the
-    Gram product 4nDm m_f, the QP product 2D(n m_f)^2) and the elementwise VALU work (pair
-    projections 15 N_p H, bound balls 24nH, pair scatter 2 N_p H D, multiplier/target update
-    5nDm_f; with a workspace, its spheroid projection 12nH: offset 3, scaled norm 5, rsqrt 4
-    counted as in the balls; its back-projection shares the position product).  Returns
-    (contractions, elementwise)."""
+    """Algorithmic work of one iteration for one sample (multiply-add = 2 flops), split by the
+    unit it belongs to: the dense contractions (basis evaluation 6nDHm, back-projection to the
+    free coefficients 6nDHm_f, the Gram product 4nDm m_f, the QP product 2D(n m_f)^2) go to the
+    matrix cores; the elementwise work (pair projections 15 N_p H, bound balls 24nH, pair scatter
+    2 N_p H D, multiplier/target update 5nDm_f, with a workspace its spheroid projection 8nH) and
+    the reciprocal square roots (N_p H + 2nH, with a workspace + nH; 4 flops each) to the vector
+    ALUs.  Returns (contractions, elementwise, rsqrt count)."""
     n, D, m, H = cfg.n_robots, cfg.dims, cfg.degree + 1, cfg.horizon
     mf = m - 6
     Np = n * (n - 1) // 2
     dense = 6 * n * D * H * m + 6 * n * D * H * mf + 4 * n * D * m * mf + 2 * D * (n * mf) ** 2
     elem = 15 * Np * H + 24 * n * H + 2 * Np * H * D + 5 * n * D * mf
+    rsq = Np * H + 2 * n * H
     if getattr(cfg, "ws_a", 0.0) > 0:
-        elem += 12 * n * H
-    return dense, elem
+        elem += 8 * n * H
+        rsq += n * H
+    return dense, elem, rsq
 
 
 def flops_per_sample_iter(cfg):
-    return sum(flops_split(cfg))
+    d, e, r = flops_split(cfg)
+    return d + e + 4 * r
 
 
 def kernel_source_digest():
@@ -85,20 +88,61 @@ def measured_traffic(workload, precision):
     return int(kib * 1024)
 
 
-def cpu_baseline(problem, n_samples, iters):
-    """The FP64 oracle on a bounded sample of the same workload, on the host cores."""
-    import torch
-    import oracle as O
-    s = O.build_system(problem.cfg)
-    xb = torch.tensor(problem.xi_bar[:n_samples])
-    bv = torch.tensor(problem.bvals)
+def host_info():
+    """The host the CPU baseline runs on: logical CPUs, the ones this process may use, CPU model."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
+
+
+def _time_oracle(O, s, xb, bv, iters):
     t0 = time.perf_counter()
     O.sf_project(s, xb, bv, iters)
-    dt = time.perf_counter() - t0
-    return {"value": round(n_samples / dt, 2), "unit": "projections/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(problem, n_samples, iters):
+    """The FP64 oracle on bounded samples of the same workload, on the host cores: all threads on
+    two subset sizes (half and all of n_samples; linear scaling in samples is checked, not assumed),
+    one thread on an eighth, and the 4-robot 2D workload of the oracle's own size in full."""
+    import torch
+    import oracle as O
+    import workloads as W
+    s = O.build_system(problem.cfg)
+    bv = torch.tensor(problem.bvals)
+    threads = torch.get_num_threads()
+    half = max(1, n_samples // 2)
+    t_half = _time_oracle(O, s, torch.tensor(problem.xi_bar[:half]), bv, iters)
+    t_all = _time_oracle(O, s, torch.tensor(problem.xi_bar[:n_samples]), bv, iters)
+    one = max(1, n_samples // 8)
+    torch.set_num_threads(1)
+    try:
+        t_one = _time_oracle(O, s, torch.tensor(problem.xi_bar[:one]), bv, iters)
+    finally:
+        torch.set_num_threads(threads)
+    tiny = W.tiny2d().problems[0]
+    st = O.build_system(tiny.cfg)
+    t_tiny = _time_oracle(O, st, torch.tensor(tiny.xi_bar), torch.tensor(tiny.bvals), W.tiny2d().iters)
+    return {"value": round(n_samples / t_all, 2), "unit": "projections/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n_samples} of {problem.xi_bar.shape[0]} samples, {iters} iterations, "
-                      f"FP64 torch CPU ({dt:.1f} s)"}
+                      f"FP64 torch CPU, {threads} threads ({t_all:.1f} s)",
+            "host": host_info(),
+            "linearity": {"samples": [half, n_samples], "projections_per_s": [round(half / t_half, 2),
+                                                                              round(n_samples / t_all, 2)]},
+            "one_thread": {"samples": one, "projections_per_s": round(one / t_one, 2), "seconds": round(t_one, 2)},
+            "tiny2d_full": {"samples": tiny.xi_bar.shape[0], "iters": W.tiny2d().iters,
+                            "projections_per_s": round(tiny.xi_bar.shape[0] / t_tiny, 2),
+                            "seconds": round(t_tiny, 3)}}
 
 
 def time_calls(call, steps, warmup):
@@ -128,24 +172,34 @@ def judge(sf, out_xi, bv, prec, batch=None):
     return int(feas.sum()), float(worst.quantile(0.99)), float(worst.max())
 
 
-def roofline(cfg_counts, iters, ms, prec, traffic):
-    """Contract roofline (all algorithmic flops against the FP32 vector peak) plus the split
-    bound: contractions against the MFMA peak of their dtype, elementwise work against the
-    vector peak, the larger of the two times as the floor."""
+def roofline(cfg_counts, iters, ms, prec, traffic, generic=False):
+    """Roofline of the solve: the contractions against the matrix-core peak of their dtype and the
+    elementwise work (reciprocal square roots at 4 flops) against the vector peak; the term that
+    needs longer at peak binds, and frac = max(W_mfma / peak_mfma, W_valu / peak_valu) / t.  The
+    generic kernel (and FP64) does everything on the vector ALUs.  The dense count charges the
+    method's work; the MFMA kernel skips work whose result is exactly zero (culled pairs, inactive
+    balls), which the effective all-flops rate beside it reflects."""
     dense = sum(flops_split(c)[0] * k for c, k in cfg_counts) * iters
-    elem = sum(flops_split(c)[1] * k for c, k in cfg_counts) * iters
+    elem = sum((flops_split(c)[1] + 4 * flops_split(c)[2]) * k for c, k in cfg_counts) * iters
     t = ms / 1e3
-    peak = PEAKS["fp64_vector_tflops"] if prec == "fp64" else PEAKS["fp32_vector_tflops"]
-    achieved = (dense + elem) / t / 1e12
-    mfma_peak = PEAKS.get(f"{prec}_mfma_tflops", PEAKS["fp32_mfma_tflops"])
-    floor = max(dense / (mfma_peak * 1e12), elem / (peak * 1e12))
+    vpeak = PEAKS["fp64_vector_tflops"] if prec == "fp64" else PEAKS["fp32_vector_tflops"]
+    if generic or prec == "fp64":
+        terms = {"valu": {"flops": dense + elem, "peak": vpeak}}
+    else:
+        terms = {"mfma": {"flops": dense, "peak": PEAKS[f"{prec}_mfma_tflops"]},
+                 "valu": {"flops": elem, "peak": vpeak}}
+    for v in terms.values():
+        v["achieved"] = round(v["flops"] / t / 1e12, 3)
+        v["frac"] = round(v["flops"] / t / 1e12 / v["peak"], 4)
+        v["floor_ms"] = round(v["flops"] / (v["peak"] * 1e12) * 1e3, 4)
+    bind = max(terms, key=lambda k: terms[k]["frac"])
+    b = terms[bind]
     n_units = sum(k for _, k in cfg_counts)
-    return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": traffic,
+    return {"bound": "alu" if bind == "valu" else "mfma", "achieved": b["achieved"], "peak": b["peak"],
+            "unit": "TFLOP/s", "frac": b["frac"], "traffic": traffic, "terms": terms,
             "flops_per_sample_iter": round((dense + elem) / iters / n_units, 1), "kernel_ms": round(ms, 4),
-            "split": {"contraction_flops": dense, "elementwise_flops": elem, "mfma_peak": mfma_peak,
-                      "floor_ms": round(floor * 1e3, 4), "frac": round(floor / t, 4)},
-            "note": "dense algorithmic flops of the method; the MFMA kernel skips exact zeros"}
+            "effective_all_flops_tflops": round((dense + elem) / t / 1e12, 3),
+            "note": "dense algorithmic flops of the method against the binding unit's published peak"}
 
 
 def base_line(args, metric, value, ms, dtype, config, scaling="weak"):
@@ -244,8 +298,29 @@ def run_warmstart(args, wl):
     return line
 
 
+def equal_residual_iters(sf, xb, bv, prec, k0, ref, k_max):
+    """Smallest K >= k0 at which the form `prec` reaches the reference form's final feasibility:
+    converged count at least the reference's, p99 and maximum of the per-sample violation at most
+    the reference's.  Returns (K, criteria at K, first output at k0, trials)."""
+    import torch
+    first, trials, crit = None, [], None
+    for K in range(k0, k_max + 1):
+        out = sf.project(xb, bv, K, precision=prec, want_lam=False)
+        torch.cuda.synchronize()
+        if first is None:
+            first = out
+        n, p99, vmax = judge(sf, out.xi, bv, prec)
+        crit = {"converged": n >= ref[0], "p99": p99 <= ref[1], "max": vmax <= ref[2]}
+        trials.append({"iters": K, "converged": n, "violation_p99": p99, "violation_max": vmax})
+        if all(crit.values()):
+            return K, crit, first, trials
+    return None, crit, first, trials
+
+
 def run_single(args, wl):
-    """One problem with many samples (16- or 32-robot swarm): headline form + comparison form."""
+    """One problem with many samples (16- or 32-robot swarm).  The comparison form (plain FP32) runs
+    the workload's K; the headline form runs the smallest K at which its final feasibility is at
+    least as good (equal residual), and is timed there."""
     import torch
     from paper_2501_19042_amd import SafetyFilter
     p = wl.problems[0]
@@ -256,22 +331,34 @@ def run_single(args, wl):
     bv = torch.tensor(p.bvals, dtype=dt, device="cuda")
     S, K = xb.shape[0], wl.iters
 
-    def form(pr, steps, warmup):
+    def form(pr, iters, steps, warmup):
         bufs = None
         if args.graph:
             from paper_2501_19042_amd import ProjectResult
             bufs = ProjectResult(torch.empty_like(xb), torch.empty_like(xb),
                                  torch.empty((S, 2), dtype=xb.dtype, device=xb.device), None)
-        call = lambda: sf.project(xb, bv, K, precision=pr, generic=args.generic, graph=args.graph, out=bufs,
+        call = lambda: sf.project(xb, bv, iters, precision=pr, generic=args.generic, graph=args.graph, out=bufs,
                                   autotune=args.autotune and not args.generic)
         return time_calls(call, steps, warmup)
 
-    ms, out = form(prec, args.steps, args.warmup)
+    compare = args.compare != "none" and args.compare != prec and prec != "fp64"
+    k_head, eq = K, None
+    if compare:
+        ms2, out2 = form(args.compare, K, args.steps, args.warmup)
+        n2, p99b, vmaxb = judge(sf, out2.xi, bv, args.compare)
+        k_eq, crit, first, trials = equal_residual_iters(sf, xb, bv, prec, K, (n2, p99b, vmaxb),
+                                                         K + args.equal_residual_slack)
+        dev = ((first.xi - out2.xi).abs().reshape(S, -1).amax(1) / out2.xi.abs().reshape(S, -1).amax(1)).cpu()
+        eq = {"reference": {"precision": args.compare, "iters": K}, "iters": k_eq, "reached": k_eq is not None,
+              "criteria": crit, "trials": trials[:3] + (trials[-2:] if len(trials) > 5 else trials[3:])}
+        if k_eq is not None:
+            k_head = k_eq
+    ms, out = form(prec, k_head, args.steps, args.warmup)
     n_conv, p99, vmax = judge(sf, out.xi, bv, prec)
     traffic = None if (args.generic or prec == "fp64") else measured_traffic(args.workload, prec)
     ws = getattr(p.cfg, "ws_a", 0.0) > 0
     config = {"workload": wl.name, "samples": S, "robots": p.cfg.n_robots, "dims": p.cfg.dims,
-              "degree": p.cfg.degree, "horizon": p.cfg.horizon, "iters": K, "precision": prec,
+              "degree": p.cfg.degree, "horizon": p.cfg.horizon, "iters": k_head, "precision": prec,
               "kernel": "generic" if args.generic else "mfma", "graph": args.graph,
               "launch_shape": "autotuned" if args.autotune else "plan default"}
     if ws:
@@ -283,16 +370,15 @@ def run_single(args, wl):
                      "BF16-MFMA vs FP32 at equal residual", n_conv / (ms / 1e3), ms, DTYPES[prec], config)
     line.update({"converged_fraction": round(n_conv / S, 6), "violation_p99": p99, "violation_max": vmax,
                  "all_samples_per_s": round(S / (ms / 1e3), 1),
-                 "roofline": roofline([(p.cfg, S)], K, ms, prec, traffic)})
-    if args.compare != "none" and args.compare != prec and prec != "fp64":
-        ms2, out2 = form(args.compare, args.steps, args.warmup)
-        n2, p99b, vmaxb = judge(sf, out2.xi, bv, args.compare)
-        dev = ((out.xi - out2.xi).abs().reshape(S, -1).amax(1) / out2.xi.abs().reshape(S, -1).amax(1)).cpu()
+                 "roofline": roofline([(p.cfg, S)], k_head, ms, prec, traffic, generic=args.generic)})
+    if compare:
+        line["equal_residual"] = eq
         line["compare"] = {
-            "precision": args.compare, "ms_per_step": round(ms2, 4), "value": round(n2 / (ms2 / 1e3), 1),
+            "precision": args.compare, "iters": K, "ms_per_step": round(ms2, 4), "value": round(n2 / (ms2 / 1e3), 1),
             "converged_fraction": round(n2 / S, 6), "violation_p99": p99b, "violation_max": vmaxb,
             "speedup_of_headline": round(ms2 / ms, 3),
-            "per_sample_rel_deviation_max": float(dev.max()), "per_sample_rel_deviation_median": float(dev.median()),
+            "roofline_frac": roofline([(p.cfg, S)], K, ms2, args.compare, None)["frac"],
+            "per_sample_rel_deviation_at_equal_iters": {"max": float(dev.max()), "median": float(dev.median())},
         }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, min(args.cpu_samples, S), K)
@@ -369,6 +455,9 @@ def main():
     ap.add_argument("--compare", default="fp32", choices=["fp32", "bf16", "fp16", "none"],
                     help="second form timed beside the headline one")
     ap.add_argument("--cpu-samples", type=int, default=64)
+    ap.add_argument("--equal-residual-slack", type=int, default=60,
+                    help="most extra iterations the headline form may take to reach the comparison form's "
+                         "final feasibility")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--generic", action="store_true", help="force the generic (non-MFMA) kernel")
     ap.add_argument("--graph", action="store_true", help="replay the launch as a captured hipGraph")

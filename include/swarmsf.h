@@ -73,6 +73,21 @@ typedef enum {
 #define SF_PERSISTENT 16     /* run a single-shape batch through the persistent work-queue kernel (a
                                 batch of mixed swarm sizes always uses it on the MFMA path) */
 
+/* Per-sample status bits written by sf_project into status_out (0 = finite and converged).
+ *  SF_SAMPLE_NONFINITE_INPUT  a coefficient of the sample's xi_bar, xi0 or lam0, or a boundary value of
+ *                             its problem, is NaN or infinite.  The sample is not iterated: its xi_out,
+ *                             lam_out and resid_out entries are NaN.  Other samples are unaffected.
+ *  SF_SAMPLE_NONFINITE        from finite inputs, the iteration produced a NaN or infinity (overflow);
+ *                             it stays in the state, so it shows in xi_out / lam_out / resid_out
+ *  SF_SAMPLE_NOT_CONVERGED    the largest Euclidean norm of one constraint's block of the final primal
+ *                             residual (eq. primal_residual) exceeds SF_CONV_TOL (iters >= 1 only; an
+ *                             infeasible problem keeps this bit however long it runs).
+ * The finiteness tests are bit tests on the IEEE encoding, so they hold in every kernel. */
+#define SF_SAMPLE_NONFINITE_INPUT 1
+#define SF_SAMPLE_NONFINITE 2
+#define SF_SAMPLE_NOT_CONVERGED 4
+#define SF_CONV_TOL 1e-3     /* m, m/s, m/s^2: the feasibility tolerance of the benchmark's judge */
+
 /* One problem shape (eqs. poly, inter_robot_con, workspace_con; the velocity and acceleration
  * bounds are origin-centred balls in the polar form of eq. workspace_polar with d in [0, 1]).
  *  n_robots >= 2, dims in {2, 3}, degree >= 5 (Bernstein), horizon >= degree + 1,
@@ -122,6 +137,9 @@ void sf_destroy(sf_handle h);
  *  resid_out [S, 2] (or [S, iters, 2] with SF_RESID_HISTORY), or NULL:
  *          (||r_p||_2^2, largest Euclidean norm of one constraint's residual block)
  *          for the primal residual of eq. (primal_residual) after the last step.
+ *  status_out int32 [S], or NULL: per-sample SF_SAMPLE_* bits (non-finite input, non-finite result,
+ *          not converged), so that non-convergence and NaN are reported as data, not as errors.
+ *          Asking for it costs one residual pass per sample when resid_out is NULL.
  *  ckpt    [ceil(iters/ckpt_every), 2, total coefficient elements] or NULL: the state
  *          (xi^k, lambda^k) at k = 0, c, 2c, ... (c = ckpt_every >= 1), as needed by
  *          sf_project_backward.
@@ -133,7 +151,7 @@ void sf_destroy(sf_handle h);
 sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision,
                      const void* xi_bar, const void* bvals,
                      const void* xi0, const void* lam0, int32_t iters,
-                     void* xi_out, void* lam_out, void* resid_out, int32_t flags,
+                     void* xi_out, void* lam_out, void* resid_out, int32_t* status_out, int32_t flags,
                      void* ckpt, int32_t ckpt_every, void* stream);
 
 /* Reverse-mode derivative of sf_project (same batch, precision, iters, xi_bar, bvals

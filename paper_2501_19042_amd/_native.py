@@ -13,6 +13,8 @@ SF_USE_GRAPH = 4
 SF_AUTOTUNE = 8
 SF_PERSISTENT = 16
 SF_FP_RESIDUAL = 32
+SF_SAMPLE_NONFINITE_INPUT, SF_SAMPLE_NONFINITE, SF_SAMPLE_NOT_CONVERGED = 1, 2, 4
+SF_CONV_TOL = 1e-3
 PRECISIONS = {"fp64": SF_FP64, "fp32": SF_FP32, "bf16": SF_BF16, "fp16": SF_FP16}
 
 EXPORTED = ["sf_setup", "sf_destroy", "sf_project", "sf_project_backward", "sf_feasibility",
@@ -55,7 +57,7 @@ def lib():
     L.sf_setup.restype = c_int32
     L.sf_destroy.argtypes = [vp]
     L.sf_destroy.restype = None
-    L.sf_project.argtypes = [vp, POINTER(SfBatch), c_int32, vp, vp, vp, vp, c_int32, vp, vp, vp, c_int32,
+    L.sf_project.argtypes = [vp, POINTER(SfBatch), c_int32, vp, vp, vp, vp, c_int32, vp, vp, vp, vp, c_int32,
                              vp, c_int32, vp]
     L.sf_project.restype = c_int32
     L.sf_project_backward.argtypes = [vp, POINTER(SfBatch), c_int32, vp, vp, c_int32, vp, c_int32,

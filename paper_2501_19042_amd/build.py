@@ -13,7 +13,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libswarmsf.so")
-SOURCES = ["sf_api.hip", "sf_generic.hip", "sf_fast.hip", "sf_adjoint.hip", "sf_eqqp.hip"]
+# the MFMA kernel instances are compiled per operand precision and workspace flag, in parallel
+FAST_INSTANCES = [f"sf_fast_p{mp}_w{ws}.hip" for mp in range(3) for ws in range(2)]
+SOURCES = FAST_INSTANCES + ["sf_fast.hip", "sf_api.hip", "sf_generic.hip", "sf_adjoint.hip", "sf_eqqp.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -21,9 +23,12 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
-# The MFMA kernels never take NaN operands (inputs are validated coordinates); without NaN
-# semantics min/max lower to single instructions instead of canonicalize + min.
-FILE_FLAGS = {"sf_fast.hip": ["-fno-honor-nans"]}
+# The MFMA kernels are compiled without NaN semantics, so that min/max lower to single instructions
+# instead of canonicalize + min.  A NaN can still reach them: each sample's inputs (coefficients,
+# initial state, boundary values) and its results are checked with bit tests on the IEEE encoding
+# (kept opaque to the compiler, see nonfinite_bits) and reported in the per-sample status; a sample
+# with a non-finite input is not iterated.
+FILE_FLAGS = {f: ["-fno-honor-nans"] for f in FAST_INSTANCES}
 
 
 def _run(cmd, verbose):
@@ -44,7 +49,7 @@ def build(verbose: bool = False) -> str:
     for s in SOURCES:
         obj = os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o")
         jobs.append((obj, [hipcc] + FLAGS + FILE_FLAGS.get(s, []) + inc + ["-c", os.path.join(CSRC, s), "-o", obj]))
-    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", "4"))))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", str(os.cpu_count() or 4)))))
     with concurrent.futures.ThreadPoolExecutor(workers) as ex:
         for f in [ex.submit(_run, cmd, verbose) for _, cmd in jobs]:
             f.result()

@@ -425,7 +425,7 @@ bool tune_lookup(const std::string& sig, int* waves, int* grid) {
     char key[256];
     int w = 0, g = 0;
     if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"waves\": %d, \"grid\": %d", key, &w, &g) == 3 &&
-        sig == key && (w == 2 || w == 4)) {
+        sig == key && w >= 2 && w <= 4) {
       *waves = w;
       *grid = g;
       found = true;
@@ -658,8 +658,8 @@ void sf_destroy(sf_handle h) {
 
 sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, const void* xi_bar,
                      const void* bvals, const void* xi0, const void* lam0, int32_t iters, void* xi_out,
-                     void* lam_out, void* resid_out, int32_t flags, void* ckpt, int32_t ckpt_every,
-                     void* stream) {
+                     void* lam_out, void* resid_out, int32_t* status_out, int32_t flags, void* ckpt,
+                     int32_t ckpt_every, void* stream) {
   g_err.clear();
   if (!h) return fail(SF_EINVAL, "handle is NULL");
   if (precision < SF_FP64 || precision > SF_FP16) return fail(SF_EINVAL, "unknown precision");
@@ -675,6 +675,7 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
   const void* ptrs[] = {xi_bar, bvals, xi0, lam0, xi_out, lam_out, resid_out, ckpt};
   for (const void* q : ptrs)
     if (q && !aligned(q, elem)) return fail(SF_EINVAL, "misaligned array");
+  if (status_out && !aligned(status_out, sizeof(int32_t))) return fail(SF_EINVAL, "misaligned status array");
   std::lock_guard<std::mutex> lock(h->mu);
   sf_status st = check_device(h);
   if (st != SF_OK) return st;
@@ -687,7 +688,7 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
   a.items = p->d_items;
   a.n_items = p->n_items;
   a.xi_bar = xi_bar; a.bvals = bvals; a.xi0 = xi0; a.lam0 = lam0; a.iters = iters;
-  a.xi_out = xi_out; a.lam_out = lam_out; a.resid_out = resid_out;
+  a.xi_out = xi_out; a.lam_out = lam_out; a.resid_out = resid_out; a.status_out = status_out;
   a.flags = flags & (SF_RESID_HISTORY | SF_FP_RESIDUAL);
   a.ckpt = ckpt; a.ckpt_every = ckpt ? ckpt_every : 1; a.ckpt_stride = p->total_coef;
   a.stream = static_cast<hipStream_t>(stream);
@@ -734,7 +735,8 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
                                   (uintptr_t)fp, (uintptr_t)(fp ? fp->tuned_grid[precision & 3] : 0),
                                   (uintptr_t)(fp ? fp->tuned_w[precision & 3] : 0),
                                   (uintptr_t)xi_bar, (uintptr_t)bvals, (uintptr_t)xi0, (uintptr_t)lam0,
-                                  (uintptr_t)xi_out, (uintptr_t)lam_out, (uintptr_t)resid_out, (uintptr_t)ckpt};
+                                  (uintptr_t)xi_out, (uintptr_t)lam_out, (uintptr_t)resid_out,
+                                  (uintptr_t)status_out, (uintptr_t)ckpt};
     hipGraphExec_t exec = nullptr;
     for (auto& g : p->graphs)
       if (g.key == key) exec = g.exec;

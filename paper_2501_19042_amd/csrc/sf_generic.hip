@@ -30,7 +30,8 @@ generic_project_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ ta
                        const DevProblem* __restrict__ probs, const WorkItem* __restrict__ items, int n_items,
                        const T* __restrict__ xi_bar, const T* __restrict__ bvals,
                        const T* __restrict__ xi0, const T* __restrict__ lam0, int iters,
-                       T* __restrict__ xi_out, T* __restrict__ lam_out, T* __restrict__ resid_out, int flags,
+                       T* __restrict__ xi_out, T* __restrict__ lam_out, T* __restrict__ resid_out,
+                       int32_t* __restrict__ status_out, int flags,
                        T* __restrict__ ckpt, int ckpt_every, int64_t ckpt_stride, int TT) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
@@ -49,6 +50,33 @@ generic_project_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ ta
       const int64_t sidx = pr.sample_base + sl;
       setup_sample<T>(x, L, xi_bar + coef, bvals + pr.bnd_off, xi0 ? xi0 + coef : nullptr,
                       lam0 ? lam0 + coef : nullptr);
+      // a sample with a NaN or infinite input is not iterated: its outputs are NaN
+      int bad = 0;
+      for (int q = threadIdx.x; q < nDm; q += blockDim.x)
+        bad |= nonfinite_bits(L.xb[q]) | nonfinite_bits(L.xi[q]) | nonfinite_bits(L.lam[q]);
+      for (int q = threadIdx.x; q < x.nD6; q += blockDim.x) bad |= nonfinite_bits(bvals[pr.bnd_off + q]);
+      if (__syncthreads_or(bad)) {
+        const T qnan = sizeof(T) == 8 ? T(quiet_nan_f64()) : T(quiet_nan_f32());
+        for (int q = threadIdx.x; q < nDm; q += blockDim.x) {
+          xi_out[coef + q] = qnan;
+          if (lam_out) lam_out[coef + q] = qnan;
+          if (ckpt)
+            for (int k = 0; k < iters; k += ckpt_every) {
+              const int64_t base = (int64_t)(k / ckpt_every) * 2 * ckpt_stride + coef;
+              ckpt[base + q] = qnan;
+              ckpt[base + ckpt_stride + q] = qnan;
+            }
+        }
+        if (resid_out) {
+          const int64_t nr = history ? (int64_t)iters * 2 : rw;
+          for (int64_t q = threadIdx.x; q < nr; q += blockDim.x) resid_out[sidx * nr + q] = qnan;
+        }
+        if (status_out && threadIdx.x == 0) status_out[sidx] = SF_SAMPLE_NONFINITE_INPUT;
+        __syncthreads();
+        continue;
+      }
+      const bool final_resid = (resid_out || status_out) && !(history && resid_out);
+      T last_mx = T(0);   // largest block norm of the last residual in history mode
       T fsum = T(0);   // this thread's share of the fixed-point residual sum
       for (int k = 0; k < iters; ++k) {
         if (ckpt && (k % ckpt_every) == 0) {
@@ -58,7 +86,7 @@ generic_project_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ ta
             ckpt[base + ckpt_stride + q] = L.lam[q];
           }
         }
-        if (history || fpr || (resid_out && k == iters - 1))
+        if (history || fpr || (final_resid && k == iters - 1))
           for (int q = threadIdx.x; q < nDm; q += blockDim.x) L.xprev[q] = L.xi[q];
         iteration<T>(x, L, TT, k);
         if (fpr) {
@@ -77,26 +105,31 @@ generic_project_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ ta
             resid_out[(sidx * iters + k) * 2 + 0] = ss;
             resid_out[(sidx * iters + k) * 2 + 1] = mx;
           }
+          last_mx = mx;
         }
       }
-      if (resid_out && !history) {
+      if (final_resid) {
         T ss = T(0), mx = T(0);
         if (iters > 0) residual_pass<T>(x.c, x.basis, L, TT, ss, mx);
         if (fpr) {
           T unused = T(0);
           block_reduce_sum_max<T>(L.red, fsum, unused);
         }
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == 0 && resid_out) {
           resid_out[sidx * rw + 0] = ss;
           resid_out[sidx * rw + 1] = mx;
           if (fpr) resid_out[sidx * rw + 2] = fsum;
         }
+        last_mx = mx;
       }
+      int bad_out = 0;
       for (int q = threadIdx.x; q < nDm; q += blockDim.x) {
         xi_out[coef + q] = L.xi[q];
         if (lam_out) lam_out[coef + q] = L.lam[q];
+        bad_out |= nonfinite_bits(L.xi[q]) | nonfinite_bits(L.lam[q]);
       }
-      __syncthreads();
+      bad_out = __syncthreads_or(bad_out);
+      if (status_out && threadIdx.x == 0) status_out[sidx] = sample_status<T>(false, bad_out != 0, last_mx, iters);
     }
   }
 }
@@ -223,7 +256,7 @@ hipError_t launch_generic_project(const LaunchArgs& a) {
                      static_cast<const T*>(a.xi_bar), static_cast<const T*>(a.bvals),
                      static_cast<const T*>(a.xi0), static_cast<const T*>(a.lam0), a.iters,
                      static_cast<T*>(a.xi_out), static_cast<T*>(a.lam_out), static_cast<T*>(a.resid_out),
-                     a.flags, static_cast<T*>(a.ckpt), a.ckpt_every, a.ckpt_stride, a.tile);
+                     a.status_out, a.flags, static_cast<T*>(a.ckpt), a.ckpt_every, a.ckpt_stride, a.tile);
   return hipGetLastError();
 }
 

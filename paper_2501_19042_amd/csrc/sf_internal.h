@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "swarmsf.h"
+
 namespace sf {
 
 constexpr int kBlock = 256;          // threads per workgroup of the generic kernels
@@ -64,6 +66,7 @@ struct LaunchArgs {
   void* xi_out;
   void* lam_out;
   void* resid_out;
+  int32_t* status_out;           // per-sample SF_SAMPLE_* bits, or NULL
   int32_t flags;
   void* ckpt;
   int32_t ckpt_every;
@@ -72,6 +75,45 @@ struct LaunchArgs {
   size_t lds_bytes;
   hipStream_t stream;
 };
+
+// Bit test for NaN and infinity on the IEEE encoding (all exponent bits set).  The integer goes
+// through an empty asm statement first: otherwise the compiler recognises the pattern as a
+// floating-point class test, which it may fold for NaN under no-NaN semantics (the MFMA kernels
+// are built that way).
+template <typename U>
+__host__ __device__ inline U opaque_bits(U u) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(u));
+#else
+  asm volatile("" : "+r"(u));
+#endif
+  return u;
+}
+__host__ __device__ inline bool nonfinite_bits(float x) {
+  return (opaque_bits(__builtin_bit_cast(uint32_t, x)) & 0x7f800000u) == 0x7f800000u;
+}
+__host__ __device__ inline bool nonfinite_bits(double x) {
+  return (opaque_bits(__builtin_bit_cast(uint64_t, x)) & 0x7ff0000000000000ull) == 0x7ff0000000000000ull;
+}
+
+// A quiet NaN built from its bit pattern (a NaN literal is undefined under no-NaN semantics).
+__host__ __device__ inline float quiet_nan_f32() { return __builtin_bit_cast(float, opaque_bits(0x7fc00000u)); }
+__host__ __device__ inline double quiet_nan_f64() {
+  return __builtin_bit_cast(double, opaque_bits(0x7ff8000000000000ull));
+}
+
+// Per-sample status (SF_SAMPLE_* bits of swarmsf.h) from what the kernel found: a non-finite input,
+// a non-finite value in the result, and the largest block norm of the final primal residual
+// (convergence is judged only after at least one iteration).
+template <typename T>
+__host__ __device__ inline int32_t sample_status(bool bad_input, bool bad_output, T resid_max, int iters) {
+  if (bad_input) return SF_SAMPLE_NONFINITE_INPUT;
+  int32_t s = 0;
+  if (bad_output) s |= SF_SAMPLE_NONFINITE;
+  if (nonfinite_bits(resid_max)) s |= SF_SAMPLE_NONFINITE | (iters > 0 ? SF_SAMPLE_NOT_CONVERGED : 0);
+  else if (iters > 0 && resid_max > T(SF_CONV_TOL)) s |= SF_SAMPLE_NOT_CONVERGED;
+  return s;
+}
 
 // Generic fused kernels (any shape that fits the LDS plan), T = double or float.
 template <typename T>

@@ -11,7 +11,7 @@ import torch
 
 from . import _native as N
 
-ProjectResult = namedtuple("ProjectResult", ["xi", "lam", "resid", "ckpt"])
+ProjectResult = namedtuple("ProjectResult", ["xi", "lam", "resid", "ckpt", "status"], defaults=(None,))
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -97,8 +97,11 @@ class SafetyFilter:
                 precision: str = "fp32", xi0: Optional[torch.Tensor] = None, lam0: Optional[torch.Tensor] = None,
                 want_lam: bool = True, want_resid: bool = True, history: bool = False,
                 ckpt_every: int = 0, generic: bool = False, graph: bool = False, autotune: bool = False,
-                persistent: bool = False, fp_residual: bool = False, out: Optional[ProjectResult] = None,
-                stream=None) -> ProjectResult:
+                persistent: bool = False, fp_residual: bool = False, want_status: bool = False,
+                out: Optional[ProjectResult] = None, stream=None) -> ProjectResult:
+        """sf_project on device tensors.  With want_status, `status` holds per-sample int32 bits
+        (SF_SAMPLE_NONFINITE_INPUT, SF_SAMPLE_NONFINITE, SF_SAMPLE_NOT_CONVERGED; 0 = finite and
+        converged)."""
         prec = N.PRECISIONS[precision]
         dtype = torch.float64 if prec == N.SF_FP64 else torch.float32
         batch = self._batch(batch, xi_bar)
@@ -106,8 +109,9 @@ class SafetyFilter:
         for t, nm, ne in ((xi_bar, "xi_bar", coef), (bvals, "bvals", bnd), (xi0, "xi0", coef), (lam0, "lam0", coef)):
             self._check(t, nm, dtype, ne)
         if out is not None:           # caller-provided outputs (fixed addresses, e.g. for graph replay)
-            xi_out, lam_out, resid, ckpt = out
+            xi_out, lam_out, resid, ckpt, status = out
         else:
+            status = torch.empty((S,), dtype=torch.int32, device=self.device) if want_status else None
             xi_out = torch.empty_like(xi_bar)
             lam_out = torch.empty_like(xi_bar) if want_lam else None
             resid = None
@@ -122,9 +126,9 @@ class SafetyFilter:
                  | (N.SF_USE_GRAPH if graph else 0) | (N.SF_AUTOTUNE if autotune else 0)
                  | (N.SF_PERSISTENT if persistent else 0) | (N.SF_FP_RESIDUAL if fp_residual else 0))
         N.check(N.lib().sf_project(self._h, ctypes.byref(batch.c), prec, _ptr(xi_bar), _ptr(bvals), _ptr(xi0),
-                                   _ptr(lam0), int(iters), _ptr(xi_out), _ptr(lam_out), _ptr(resid), flags,
-                                   _ptr(ckpt), int(ckpt_every), _stream_ptr(stream)))
-        return ProjectResult(xi_out, lam_out, resid, ckpt)
+                                   _ptr(lam0), int(iters), _ptr(xi_out), _ptr(lam_out), _ptr(resid), _ptr(status),
+                                   flags, _ptr(ckpt), int(ckpt_every), _stream_ptr(stream)))
+        return ProjectResult(xi_out, lam_out, resid, ckpt, status)
 
     def project_backward(self, xi_bar, bvals, iters, ckpt, ckpt_every, g_xi_out=None, g_lam_out=None,
                          g_resid=None, batch: Optional[Batch] = None, precision: str = "fp32",

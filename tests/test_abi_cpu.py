@@ -124,6 +124,24 @@ def test_factor_table_capacity_check():
 def test_null_arguments_are_errors_not_crashes():
     L = N.lib()
     assert L.sf_setup(None, 0, None) == N.SF_EINVAL
-    assert L.sf_project(None, None, 1, None, None, None, None, 1, None, None, None, 0, None, 0, None) == N.SF_EINVAL
+    assert L.sf_project(None, None, 1, None, None, None, None, 1, None, None, None, None, 0, None, 0, None) == N.SF_EINVAL
     assert L.sf_feasibility(None, None, 1, None, None, None, None) == N.SF_EINVAL
     L.sf_destroy(None)
+
+
+@pytest.mark.parametrize("source", ["sf_generic.hip", "sf_fast_p1_w0.hip"])
+def test_sample_status_logic_on_the_host(tmp_path, source):
+    """The per-sample status bits (non-finite input, non-finite result, not converged against the
+    tolerance) and the NaN/infinity bit tests the kernels use, compiled for the host with the
+    optimisation and floating-point flags of each kernel source (the MFMA kernels assume no NaNs,
+    under which a plain bit test for NaN can be folded away) and run."""
+    import subprocess
+    from paper_2501_19042_amd import build as B
+    exe = tmp_path / "status_logic"
+    csrc = os.path.join(ROOT, "paper_2501_19042_amd", "csrc")
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    flags = [f for f in B.FLAGS if f not in ("-fPIC",)] + B.FILE_FLAGS.get(source, [])
+    subprocess.run([hipcc] + flags + ["-I", os.path.join(ROOT, "include"), "-I", csrc,
+                    "-o", str(exe), os.path.join(ROOT, "tests", "status_logic.cpp")], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0 and r.stdout.strip().splitlines()[-1] == "0", r.stdout

@@ -156,6 +156,8 @@ def test_every_launch_shape_matches_oracle(P, tmp_path, monkeypatch, prec, n):
         cache.write_text('{"key": "%s", "waves": %d, "grid": 0, "ms": 1.0}\n' % (key, w))
         out = P.SafetyFilter([p.cfg]).project(xb, bv, iters, precision=prec, autotune=True)
         torch.cuda.synchronize()
+        # the pinned entry was used as it stands: no trial ran, so nothing was appended
+        assert len(cache.read_text().splitlines()) == 1, (w, cache.read_text())
         g = out.xi.cpu().double().reshape(6, -1)
         e = ((g - rx.reshape(6, -1)).abs().amax(1) / rx.reshape(6, -1).abs().amax(1)).numpy()
         print(f"n={n} {prec} W={w}: max rel err {e.max():.2e}", flush=True)

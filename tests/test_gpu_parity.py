@@ -296,7 +296,7 @@ def test_flag_combinations_are_checked(lib):
     res = torch.empty((2, 3), dtype=torch.float64).cuda()
     batch = sf._batch(None, xb)
     call = lambda flags, r: N.lib().sf_project(sf._h, ctypes.byref(batch.c), N.SF_FP64, xb.data_ptr(), bv.data_ptr(),
-                                               None, None, 5, out.data_ptr(), None, r, flags, None, 0, None)
+                                               None, None, 5, out.data_ptr(), None, r, None, flags, None, 0, None)
     assert call(N.SF_FP_RESIDUAL, None) == N.SF_EINVAL
     assert call(N.SF_FP_RESIDUAL | N.SF_RESID_HISTORY, res.data_ptr()) == N.SF_EINVAL
     assert call(1 << 20, res.data_ptr()) == N.SF_EINVAL
@@ -328,7 +328,7 @@ def test_empty_batches_are_refused(lib):
     _say("case empty batches")
     for b in (N.SfBatch(0, as_p(slots), as_p(two)), N.SfBatch(1, as_p(slots), as_p(zero))):
         assert L.sf_project(sf._h, ctypes.byref(b), N.SF_FP64, xb.data_ptr(), bv.data_ptr(), None, None, 5,
-                            out.data_ptr(), None, None, 0, None, 0, None) == N.SF_EINVAL
+                            out.data_ptr(), None, None, None, 0, None, 0, None) == N.SF_EINVAL
         assert len(L.sf_last_error()) > 0
         assert L.sf_feasibility(sf._h, ctypes.byref(b), N.SF_FP64, xb.data_ptr(), bv.data_ptr(),
                                 viol.data_ptr(), None) == N.SF_EINVAL
