@@ -199,6 +199,22 @@ sf_status sf_qp_equality(sf_handle h, const sf_batch* batch, int32_t precision, 
 sf_status sf_qp_equality_backward(sf_handle h, const sf_batch* batch, int32_t precision, const void* g_out,
                                   void* g_xi_in, void* g_bvals, void* stream);
 
+/* Allocation-free variant of sf_qp_equality_backward, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments and results, bit for bit.  Instead of the handle's plan tables and its partial-sum buffer
+ * (both allocated on first use), it builds the batch's problem and chunk tables with a kernel and keeps
+ * them and the per-chunk partial sums in a fixed 16 MiB device array of the library (one per GPU,
+ * located at sf_setup, held until the process ends).  It calls no allocating routine.
+ *  Limits: at most 64 problems per call, and tables plus partial sums within the 16 MiB (about
+ *  (n_chunks x largest n D 6) elements, chunks of max(1, 32768 / (n D m)) samples per problem;
+ *  roughly 900K samples of 16 robots in FP32); beyond them SF_EUNSUPPORTED, before anything is
+ *  enqueued.
+ *  Every call on one GPU shares that array, which keeps the last call's contents: calls that overlap
+ *  in time on one GPU (any handle, any stream) race.  Nothing in it needs clearing: each call writes
+ *  every entry it reads. */
+sf_status sf_qp_equality_backward_noalloc(sf_handle h, const sf_batch* batch, int32_t precision, const void* g_out,
+                                          void* g_xi_in, void* g_bvals, void* stream);
+
 /* Host-only inspection of the FP64 factor table sf_setup builds for one config (needs no
  * GPU).  Writes a 16-double header (m, m_f, H, n, then element offsets of basis, X1, X01,
  * Bmap, Gfx, Rfx into the table that follows) and the table; *needed receives the

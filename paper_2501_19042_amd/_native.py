@@ -18,7 +18,8 @@ SF_CONV_TOL = 1e-3
 PRECISIONS = {"fp64": SF_FP64, "fp32": SF_FP32, "bf16": SF_BF16, "fp16": SF_FP16}
 
 EXPORTED = ["sf_setup", "sf_destroy", "sf_project", "sf_project_backward", "sf_feasibility",
-            "sf_qp_equality", "sf_qp_equality_backward", "sf_factor_table", "sf_last_error"]
+            "sf_qp_equality", "sf_qp_equality_backward", "sf_qp_equality_backward_noalloc", "sf_factor_table",
+            "sf_last_error"]
 
 
 class SfConfig(ctypes.Structure):
@@ -69,6 +70,8 @@ def lib():
     L.sf_qp_equality.restype = c_int32
     L.sf_qp_equality_backward.argtypes = [vp, POINTER(SfBatch), c_int32, vp, vp, vp, vp]
     L.sf_qp_equality_backward.restype = c_int32
+    L.sf_qp_equality_backward_noalloc.argtypes = [vp, POINTER(SfBatch), c_int32, vp, vp, vp, vp]
+    L.sf_qp_equality_backward_noalloc.restype = c_int32
     L.sf_factor_table.argtypes = [POINTER(SfConfig), POINTER(c_double), c_int64, POINTER(c_int64)]
     L.sf_factor_table.restype = c_int32
     L.sf_last_error.argtypes = []

@@ -639,6 +639,12 @@ sf_status sf_setup(const sf_config* cfgs, int32_t n_cfgs, sf_handle* out) {
     sf_destroy(h);
     return hip_fail(e, "sf_setup upload");
   }
+  // device address of the allocation-free entry point's array on this device (once per device)
+  e = sf::eq_noalloc_init(h->device);
+  if (e != hipSuccess) {
+    sf_destroy(h);
+    return hip_fail(e, "sf_setup: hipGetSymbolAddress of the allocation-free scratch");
+  }
   *out = h;
   return SF_OK;
 }
@@ -955,6 +961,81 @@ sf_status sf_qp_equality_backward(sf_handle h, const sf_batch* batch, int32_t pr
     e = sf::launch_qp_equality<float>(a);
   }
   if (e != hipSuccess) return hip_fail(e, "sf_qp_equality_backward launch");
+  return SF_OK;
+}
+
+sf_status sf_qp_equality_backward_noalloc(sf_handle h, const sf_batch* batch, int32_t precision, const void* g_out,
+                                          void* g_xi_in, void* g_bvals, void* stream) {
+  g_err.clear();
+  if (!h) return fail(SF_EINVAL, "handle is NULL");
+  if (!g_out) return fail(SF_EINVAL, "g_out is required");
+  if (precision < SF_FP64 || precision > SF_FP16) return fail(SF_EINVAL, "unknown precision");
+  const size_t elem = precision == SF_FP64 ? sizeof(double) : sizeof(float);
+  if (!aligned(g_out, elem) || (g_xi_in && !aligned(g_xi_in, elem)) || (g_bvals && !aligned(g_bvals, elem)))
+    return fail(SF_EINVAL, "misaligned array");
+  if (!batch) return fail(SF_EINVAL, "batch is NULL");
+  if (batch->n_problems < 1) return fail(SF_EINVAL, "batch has no problems");
+  if (!batch->cfg_slot || !batch->sample_count) return fail(SF_EINVAL, "batch arrays are NULL");
+  if (batch->n_problems > sf::kEqNoAllocMaxProblems)
+    return fail(SF_EUNSUPPORTED, "sf_qp_equality_backward_noalloc takes at most " +
+                                     std::to_string(sf::kEqNoAllocMaxProblems) + " problems per call");
+  if (!g_xi_in && !g_bvals) return SF_OK;
+  std::lock_guard<std::mutex> lock(h->mu);
+  sf_status st = check_device(h);
+  if (st != SF_OK) return st;
+  // the batch's sizes, chunk count and the most LDS any of its problems needs, without a plan
+  // (building one allocates device memory)
+  sf::EqNoAllocBatch b{};
+  b.n_probs = batch->n_problems;
+  int64_t n_chunks = 0;
+  int32_t stride = 0;
+  size_t lds = 0;
+  for (int p = 0; p < batch->n_problems; ++p) {
+    const int32_t slot = batch->cfg_slot[p], cnt = batch->sample_count[p];
+    if (slot < 0 || slot >= (int)h->cfgs.size()) return fail(SF_EINVAL, "cfg_slot out of range");
+    if (cnt < 1) return fail(SF_EINVAL, "sample_count must be >= 1");
+    const sf::DevCfg& c = h->cfgs[slot].dev;
+    const int per = std::max(1, 32768 / (c.n * c.D * c.m));
+    n_chunks += (cnt + per - 1) / per;
+    stride = std::max(stride, c.n * c.D * sf::kNFix);
+    lds = std::max(lds, sf::qp_equality_lds_bytes(c, elem));
+    b.slot[p] = slot;
+    b.count[p] = cnt;
+  }
+  const sf::EqNoAllocLayout lay =
+      sf::eq_noalloc_layout(b.n_probs, (int32_t)std::min<int64_t>(n_chunks, INT32_MAX), stride, elem);
+  if (n_chunks > INT32_MAX || lay.total > sf::kEqNoAllocBytes)
+    return fail(SF_EUNSUPPORTED, "batch needs " + std::to_string(lay.total) + " bytes of tables and partial sums; "
+                                 "the allocation-free scratch holds " + std::to_string(sf::kEqNoAllocBytes));
+  unsigned char* base = static_cast<unsigned char*>(sf::eq_noalloc_scratch(h->device));
+  if (!base) return fail(SF_EDEVICE, "allocation-free scratch was not set up on this device");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = sf::launch_eq_noalloc_tables(h->d_cfgs, b, base, lay, s);
+  if (e != hipSuccess) return hip_fail(e, "sf_qp_equality_backward_noalloc tables");
+  sf::EqArgs a{};
+  a.cfgs = h->d_cfgs;
+  a.probs = reinterpret_cast<const sf::DevProblem*>(base + lay.probs);
+  a.n_probs = b.n_probs;
+  a.chunks = reinterpret_cast<const sf::WorkItem*>(base + lay.chunks);
+  a.n_chunks = (int32_t)n_chunks;
+  a.chunk_first = reinterpret_cast<const int32_t*>(base + lay.chunk_first);
+  a.forward = false;
+  a.in = g_out;
+  a.out = g_xi_in;
+  a.part = g_bvals ? base + lay.part : nullptr;
+  a.part_stride = stride;
+  a.max_rows = stride / sf::kNFix;
+  a.g_bvals = g_bvals;
+  a.lds_bytes = lds;
+  a.stream = s;
+  if (precision == SF_FP64) {
+    a.tab = h->d_tab64;
+    e = sf::launch_qp_equality<double>(a);
+  } else {
+    a.tab = h->d_tab32;
+    e = sf::launch_qp_equality<float>(a);
+  }
+  if (e != hipSuccess) return hip_fail(e, "sf_qp_equality_backward_noalloc launch");
   return SF_OK;
 }
 

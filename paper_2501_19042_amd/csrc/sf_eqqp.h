@@ -27,6 +27,29 @@ struct EqArgs {
 
 size_t qp_equality_lds_bytes(const DevCfg& c, size_t elem);
 
+// Allocation-free reverse mode: a fixed device array of the library holds the problem and chunk
+// tables and the per-chunk partial sums.
+constexpr size_t kEqNoAllocBytes = (size_t)16 << 20;   // size of that array per GPU
+constexpr int kEqNoAllocMaxProblems = 64;               // problems per call
+struct EqNoAllocBatch {                                 // passed by value to the table kernel
+  int32_t n_probs;
+  int32_t slot[kEqNoAllocMaxProblems];
+  int32_t count[kEqNoAllocMaxProblems];
+};
+// Offsets (bytes) of the tables and the partial sums inside the array for a batch.
+struct EqNoAllocLayout {
+  size_t probs, chunks, chunk_first, part, total;
+};
+EqNoAllocLayout eq_noalloc_layout(int32_t n_probs, int32_t n_chunks, int32_t part_stride, size_t elem);
+// Device address of the array on `device` (looked up once per device, with that device current,
+// at sf_setup); nullptr before that.
+hipError_t eq_noalloc_init(int device);
+void* eq_noalloc_scratch(int device);
+// Fill the problem table, chunk table and first-chunk index of a batch into the array (the same
+// tables, in the same order, as the handle's plan for that batch).
+hipError_t launch_eq_noalloc_tables(const DevCfg* cfgs, const EqNoAllocBatch& b, void* scratch,
+                                    const EqNoAllocLayout& lay, hipStream_t stream);
+
 template <typename T>
 hipError_t launch_qp_equality(const EqArgs& a);
 

@@ -11,6 +11,7 @@
 #include "sf_eqqp.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace sf {
 namespace {
@@ -229,7 +230,90 @@ qp_equality_bsum_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ t
   }
 }
 
+// Allocation-free reverse mode: the tables of a batch, built on the device from its (config slot,
+// sample count) list, in the layout and order of the host-built plan (get_plan / get_eq_chunks):
+// problems packed in order, chunks of max(1, 32768 / (n D m)) samples.
+__global__ void __launch_bounds__(256)
+eq_noalloc_tables_kernel(const DevCfg* __restrict__ cfgs, EqNoAllocBatch b, DevProblem* __restrict__ probs,
+                         WorkItem* __restrict__ chunks, int32_t* __restrict__ chunk_first) {
+  __shared__ int32_t first[kEqNoAllocMaxProblems + 1], per[kEqNoAllocMaxProblems];
+  if (threadIdx.x == 0) {
+    int64_t coef = 0, bnd = 0, smp = 0;
+    int32_t ch = 0;
+    for (int p = 0; p < b.n_probs; ++p) {
+      const DevCfg& c = cfgs[b.slot[p]];
+      DevProblem pr;
+      pr.cfg = b.slot[p];
+      pr.count = b.count[p];
+      pr.coef_off = coef;
+      pr.bnd_off = bnd;
+      pr.sample_base = smp;
+      probs[p] = pr;
+      per[p] = max(1, 32768 / (c.n * c.D * c.m));
+      first[p] = ch;
+      chunk_first[p] = ch;
+      ch += (b.count[p] + per[p] - 1) / per[p];
+      coef += (int64_t)b.count[p] * c.n * c.D * c.m;
+      bnd += (int64_t)c.n * c.D * kNFix;
+      smp += b.count[p];
+    }
+    first[b.n_probs] = ch;
+    chunk_first[b.n_probs] = ch;
+  }
+  __syncthreads();
+  for (int p = 0; p < b.n_probs; ++p)
+    for (int q = threadIdx.x; q < first[p + 1] - first[p]; q += blockDim.x) {
+      const int s = q * per[p];
+      chunks[first[p] + q] = WorkItem{p, s, min(per[p], b.count[p] - s), 0};
+    }
+}
+
+// The array itself.  Host code never uses its name as an address: hipGetSymbolAddress gives each
+// device's copy, kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[kEqNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
 }  // namespace
+
+EqNoAllocLayout eq_noalloc_layout(int32_t n_probs, int32_t n_chunks, int32_t part_stride, size_t elem) {
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  EqNoAllocLayout l;
+  l.probs = 0;
+  l.chunks = up(l.probs + (size_t)n_probs * sizeof(DevProblem));
+  l.chunk_first = up(l.chunks + (size_t)n_chunks * sizeof(WorkItem));
+  l.part = up(l.chunk_first + (size_t)(n_probs + 1) * sizeof(int32_t));
+  l.total = l.part + (size_t)n_chunks * part_stride * elem;
+  return l;
+}
+
+hipError_t eq_noalloc_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+void* eq_noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
+hipError_t launch_eq_noalloc_tables(const DevCfg* cfgs, const EqNoAllocBatch& b, void* base,
+                                    const EqNoAllocLayout& lay, hipStream_t stream) {
+  unsigned char* s = static_cast<unsigned char*>(base);
+  hipLaunchKernelGGL(eq_noalloc_tables_kernel, dim3(1), dim3(256), 0, stream, cfgs, b,
+                     reinterpret_cast<DevProblem*>(s + lay.probs), reinterpret_cast<WorkItem*>(s + lay.chunks),
+                     reinterpret_cast<int32_t*>(s + lay.chunk_first));
+  return hipGetLastError();
+}
 
 size_t qp_equality_lds_bytes(const DevCfg& c, size_t elem) {
   return (size_t)c.n * c.D * kNFix * elem + (size_t)c.n * c.D * c.m * sizeof(int);
