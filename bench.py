@@ -432,13 +432,13 @@ def run_diff(args, wl):
     g_res = torch.ones((S,), dtype=torch.float32, device="cuda")
 
     def call():
-        out = sf.project(xb, bv, K, xi0=xb, lam0=torch.zeros_like(xb), ckpt_every=ce, generic=True)
+        out = sf.project(xb, bv, K, xi0=xb, lam0=torch.zeros_like(xb), ckpt_every=ce, fp_residual=True)
         return sf.project_backward(xb, bv, K, out.ckpt, ce, g_xi_out=g_xi, g_resid=g_res)
     ms, _ = time_calls(call, args.steps, args.warmup)
     line = base_line(args, "SF gradient evaluations/sec (16 robots, 3D, 100 unrolled iterations, checkpoints every 10)",
                      S / (ms / 1e3), ms, "f32",
                      {"workload": wl.name, "samples": S, "robots": p.cfg.n_robots, "iters": K, "ckpt_every": ce,
-                      "kernels": "generic forward with checkpoints + adjoint"})
+                      "kernels": "MFMA forward with checkpoints + adjoint"})
     line["unit"] = "gradients/s"
     return line
 

@@ -68,8 +68,8 @@ typedef enum {
                                 ~/.cache/swarmsf_tune.jsonl) for later processes */
 #define SF_FP_RESIDUAL 32    /* resid_out is [S][3]: the two residual figures, then the fixed-point
                                 residual sum over the iterations, sum_k ||xi^{k+1} - xi^k||^2 +
-                                ||lambda^{k+1} - lambda^k||^2 (the first term of eq. NN_loss); runs
-                                the generic kernel; not with SF_RESID_HISTORY */
+                                ||lambda^{k+1} - lambda^k||^2 (the first term of eq. NN_loss); not
+                                with SF_RESID_HISTORY */
 #define SF_PERSISTENT 16     /* run a single-shape batch through the persistent work-queue kernel (a
                                 batch of mixed swarm sizes always uses it on the MFMA path) */
 
@@ -145,9 +145,8 @@ void sf_destroy(sf_handle h);
  *          sf_project_backward.
  * Aliasing: outputs must not overlap inputs or each other.
  * Kernel choice is per call: SF_FP32 runs on the MFMA kernel when every problem of the batch
- * has a shape it covers (see SF_FP16) that fits its LDS plan, and none of SF_RESID_HISTORY,
- * SF_GENERIC_KERNEL or SF_FP_RESIDUAL is set; otherwise the whole batch runs on the generic
- * kernel. */
+ * has a shape it covers (see SF_FP16) that fits its LDS plan, and neither SF_RESID_HISTORY nor
+ * SF_GENERIC_KERNEL is set; otherwise the whole batch runs on the generic kernel. */
 sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision,
                      const void* xi_bar, const void* bvals,
                      const void* xi0, const void* lam0, int32_t iters,
@@ -159,8 +158,8 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision,
  * training of the initialisation.  Given cotangents of xi_out, lam_out, of
  * resid_out[:, 0] (g_resid, [S]) and of the fixed-point residual sum of SF_FP_RESIDUAL
  * (w_fpr, [S]) -- each may be NULL = zero -- it writes the gradients with respect to
- * xi0, lam0 and xi_bar (each may be NULL = not wanted).  A batch with a workspace
- * constraint (ws_a > 0) returns SF_EUNSUPPORTED. */
+ * xi0, lam0 and xi_bar (each may be NULL = not wanted).  The workspace rows of eq. (f_e) are
+ * differentiated like the bound balls (their projection's 3x3 Jacobian). */
 sf_status sf_project_backward(sf_handle h, const sf_batch* batch, int32_t precision,
                               const void* xi_bar, const void* bvals, int32_t iters,
                               const void* ckpt, int32_t ckpt_every,

@@ -77,6 +77,27 @@ __device__ __forceinline__ void ball_jt(const T* v, const T* w, int D, T lim, T*
   }
 }
 
+// J^T w for the workspace residual R(p) = q max(0, 1 - 1/||s||), q = p - p_w, s = M_w^{-1} q:
+// active (||s|| > 1): f w + rs^3 (M_w^{-2} q)(q . w) with f = 1 - rs, else 0.
+template <typename T>
+__device__ __forceinline__ void ws_jt(const T* p, const T* w, int D, const T* wc, T ia2, T ib2, T* out) {
+  T q[3] = {T(0), T(0), T(0)};
+  T ss = T(0);
+  for (int d = 0; d < D; ++d) {
+    q[d] = p[d] - wc[d];
+    ss += q[d] * q[d] * (d == 2 ? ib2 : ia2);
+  }
+  for (int d = 0; d < D; ++d) out[d] = T(0);
+  if (ss > T(1)) {
+    const T rs = rsq<T>(ss);
+    const T f = T(1) - rs;
+    T qw = T(0);
+    for (int d = 0; d < D; ++d) qw += q[d] * w[d];
+    const T k3 = rs * rs * rs * qw;
+    for (int d = 0; d < D; ++d) out[d] = f * w[d] + k3 * q[d] * (d == 2 ? ib2 : ia2);
+  }
+}
+
 // dst[q] += sum_tt basis_b[t0+tt][k] * tile_b[row][tt] over the enabled bases (no weights).
 template <typename T>
 __device__ void backproject_tile(const Ctx<T>& x, const T* tile, T* dst, int t0, int TTc, int TT) {
@@ -184,6 +205,17 @@ adjoint_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, const
                 coll_resid<T>(rp, D, x.ia2, x.ib2, x.a, x.b, i < j, R);
                 for (int d = 0; d < D; ++d) gr[d] = T(2) * gres * (rn[d] - (rp[d] - R[d]));
                 coll_jt<T>(rp, gr, D, x.ia2, x.ib2, jt);
+                for (int d = 0; d < D; ++d) {
+                  Ai[d] += gr[d];
+                  Bi[d] += jt[d] - gr[d];
+                }
+              }
+              if (c.ws_on) {   // workspace rows: r_p = p_new - e(p_prev)
+                T v[3], R[3], gr[3], jt[3];
+                for (int d = 0; d < D; ++d) v[d] = L.Y[(i * D + d) * TT + tt];
+                ws_resid<T>(v, D, x.wc, x.ws_ia2, x.ws_ib2, R);
+                for (int d = 0; d < D; ++d) gr[d] = T(2) * gres * (Wt[(i * D + d) * TT + tt] - (v[d] - R[d]));
+                ws_jt<T>(v, gr, D, x.wc, x.ws_ia2, x.ws_ib2, jt);
                 for (int d = 0; d < D; ++d) {
                   Ai[d] += gr[d];
                   Bi[d] += jt[d] - gr[d];
@@ -300,6 +332,15 @@ adjoint_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, const
                   gr[d] = x.rho_c * (Wt[(i * D + d) * TT + tt] - Wt[(j * D + d) * TT + tt]);
                 }
                 coll_jt<T>(r, gr, D, x.ia2, x.ib2, jt);
+                for (int d = 0; d < D; ++d) acc[d] += jt[d];
+              }
+              if (c.ws_on) {   // workspace rows (weight rho_w) share the position basis
+                T p[3], gr[3], jt[3];
+                for (int d = 0; d < D; ++d) {
+                  p[d] = L.Y[(i * D + d) * TT + tt];
+                  gr[d] = x.rho_c * x.ws_scale * Wt[(i * D + d) * TT + tt];
+                }
+                ws_jt<T>(p, gr, D, x.wc, x.ws_ia2, x.ws_ib2, jt);
                 for (int d = 0; d < D; ++d) acc[d] += jt[d];
               }
               for (int d = 0; d < D; ++d) GY[(i * D + d) * TT + tt] = acc[d];

@@ -701,7 +701,7 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
 
   // choose the kernel path
   sf::FastPlan* fp = nullptr;
-  if (precision != SF_FP64 && p->fast.ok && !(flags & (SF_RESID_HISTORY | SF_GENERIC_KERNEL | SF_FP_RESIDUAL))) {
+  if (precision != SF_FP64 && p->fast.ok && !(flags & (SF_RESID_HISTORY | SF_GENERIC_KERNEL))) {
     fp = &p->fast;
     if ((flags & SF_PERSISTENT) && !p->fast.batched) {
       if (!p->fast_persistent.ok) {
@@ -801,7 +801,6 @@ sf_status sf_project_backward(sf_handle h, const sf_batch* batch, int32_t precis
   int64_t max_ndm = 0;
   for (int32_t s : p->slots_used) {
     const sf::DevCfg& c = h->cfgs[s].dev;
-    if (c.ws_on) return fail(SF_EUNSUPPORTED, "the adjoint does not cover the workspace rows");
     max_ndm = std::max<int64_t>(max_ndm, (int64_t)c.n * c.D * c.m);
   }
   sf::AdjointArgs a{};

@@ -134,7 +134,7 @@ __host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W, 
   const int NT = (c.H + 15) / 16, TQ = (NT + W - 1) / W;
   int pw = p.plist + TQ * (Npmax + 1);
   if (pw < nDm) pw = nDm;
-  if (pw < 128) pw = 128;
+  if (pw < 192) pw = 192;
   p.per_wave = (pw + 3) & ~3;
   p.tiles = o;
   o += W * p.per_wave;
@@ -226,6 +226,7 @@ struct FastArgs {
   float* ckpt;
   int ckpt_every;
   int64_t ckpt_stride;
+  int fpr;               // accumulate the fixed-point residual sum (resid_out is [S][3])
 };
 
 // The whole solve of one work item (its samples) by one workgroup.  WS: the instance carries the
@@ -249,6 +250,8 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
   float* __restrict__ ckpt = A.ckpt;
   const int ckpt_every = A.ckpt_every;
   const int64_t ckpt_stride = A.ckpt_stride;
+  const bool fpr = A.fpr != 0;
+  const int rw = fpr ? 3 : 2;            // resid_out columns
   constexpr int NR = 16 * R;
   constexpr int PR = (NR * (NR - 1) / 2 + 63) / 64;   // 64-pair rounds of the broad phase
   constexpr int MFX = 4 * KS - 6;                     // free coefficients per robot-axis, at most
@@ -379,7 +382,8 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             }
         }
         if (tid == 0) {
-          if (resid_out) resid_out[sidx * 2 + 0] = resid_out[sidx * 2 + 1] = qnan;
+          if (resid_out)
+            for (int c = 0; c < rw; ++c) resid_out[sidx * rw + c] = qnan;
           if (status_out) status_out[sidx] = SF_SAMPLE_NONFINITE_INPUT;
         }
         __syncthreads();
@@ -433,6 +437,9 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
       // were built (a position is a convex combination of its coefficients, so it moves by at most
       // the largest change of a coefficient)
       float px_ = 0.0f, py_ = 0.0f, pz_ = 0.0f;
+      // this lane's share of the fixed-point residual sum_k ||xi^{k+1} - xi^k||^2 +
+      // ||lambda^{k+1} - lambda^k||^2 (multiplier/QP-step lanes; lambda changes by -g)
+      float fpsum = 0.0f;
       const float skx = (float)(c.skin * c.a) * 0.999f, skz = (float)(c.skin * c.b) * 0.999f;
 
       for (int k = 0; k < iters; ++k) {
@@ -957,6 +964,24 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             const auto sc = __builtin_amdgcn_permlane32_swap(__float_as_uint(cmax), __float_as_uint(cmax), false, false);
             cmax = fmaxf(__uint_as_float(sc[0]), __uint_as_float(sc[1]));
           }
+          if (fpr && on) {
+#pragma unroll
+            for (int j = 0; j < PF; ++j) {
+              const float g = gsum(j);
+              fpsum = fmaf(g, g, fpsum);
+              if (k == 0) {   // the pinned coefficients move to their boundary values in step 0
+                const float dx = pinned(row, hl * PF + j) - sxi[qq[j]];
+                fpsum = fmaf(dx, dx, fpsum);
+              }
+            }
+#pragma unroll
+            for (int j = 0; j < FH; ++j)
+              if (hl * FH + j < mf) {
+                const float g = gsum(PF + j);
+                fpsum = fmaf(g, g, fpsum);
+                fpsum = fmaf(acc[j], acc[j], fpsum);
+              }
+          }
           if (on) {
 #pragma unroll
             for (int j = 0; j < PF; ++j) {
@@ -1128,20 +1153,23 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         // per-wave partial sums in the wave's own region, combined in thread order
         wbuf[lane] = ss;
         wbuf[64 + lane] = mx;
+        wbuf[128 + lane] = fpsum;
         __syncthreads();
         if (tid == 0) {
-          float s = 0.0f, mm = 0.0f;
+          float s = 0.0f, mm = 0.0f, fs = 0.0f;
           for (int ww = 0; ww < W; ++ww) {
-            const float* rw = smem + L.tiles + ww * L.per_wave;
+            const float* pw = smem + L.tiles + ww * L.per_wave;
             for (int l = 0; l < 64; ++l) {
-              s += rw[l];
-              mm = fmaxf(mm, rw[64 + l]);
+              s += pw[l];
+              mm = fmaxf(mm, pw[64 + l]);
+              fs += pw[128 + l];
             }
           }
           rmax = sqrtf(mm);
           if (resid_out) {
-            resid_out[sidx * 2 + 0] = s;
-            resid_out[sidx * 2 + 1] = rmax;
+            resid_out[sidx * rw + 0] = s;
+            resid_out[sidx * rw + 1] = rmax;
+            if (fpr) resid_out[sidx * rw + 2] = fs;
           }
         }
         __syncthreads();
@@ -1204,6 +1232,7 @@ FastArgs make_fast_args(const LaunchArgs& a, const float* tab32, const uint4* a1
   f.xi_out = static_cast<float*>(a.xi_out); f.lam_out = static_cast<float*>(a.lam_out);
   f.resid_out = static_cast<float*>(a.resid_out); f.status_out = a.status_out; f.ckpt = static_cast<float*>(a.ckpt);
   f.ckpt_every = a.ckpt_every; f.ckpt_stride = a.ckpt_stride;
+  f.fpr = (a.flags & SF_FP_RESIDUAL) != 0;
   return f;
 }
 

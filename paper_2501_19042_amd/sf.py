@@ -237,8 +237,7 @@ class _SFProject(torch.autograd.Function):
     @staticmethod
     def forward(ctx, xi0, lam0, xi_bar, bvals, sf, batch, iters, ckpt_every, precision):
         out = sf.project(xi_bar.detach(), bvals.detach(), iters, batch=batch, precision=precision,
-                         xi0=xi0.detach(), lam0=lam0.detach(), ckpt_every=ckpt_every, generic=True,
-                         fp_residual=True)
+                         xi0=xi0.detach(), lam0=lam0.detach(), ckpt_every=ckpt_every, fp_residual=True)
         ctx.save_for_backward(xi_bar.detach(), bvals.detach(), out.ckpt)
         ctx.cfg = (sf, batch, iters, ckpt_every, precision)
         return out.xi, out.lam, out.resid[:, 0].contiguous(), out.resid[:, 2].contiguous()

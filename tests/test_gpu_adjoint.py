@@ -184,6 +184,28 @@ def test_fixed_point_residual_term_matches_oracle(P, iters, ce):
     assert rel_err(g1.cpu().double(), gl0) <= 1e-8
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_fixed_point_residual_sum_on_the_mfma_kernel(P, prec):
+    """SF_FP_RESIDUAL on the MFMA kernels: the per-sample sum matches the generic FP64 kernel's, the
+    checkpoints the differentiable forward writes are unchanged by the flag, and so are the
+    iterates."""
+    p = W.small3d(n_robots=16, n_samples=6, degree=10, horizon=100, seed=21,
+                  box=((-3.0, -3.0, -1.0), (3.0, 3.0, 1.0)), t_final=10.0)
+    sf = P.SafetyFilter([p.cfg])
+    xb = torch.tensor(p.xi_bar, dtype=torch.float32, device="cuda")
+    bv = torch.tensor(p.bvals, dtype=torch.float32, device="cuda")
+    _say(f"case fixed-point residual MFMA {prec}")
+    a = sf.project(xb, bv, 40, precision=prec, fp_residual=True, ckpt_every=10)
+    b = sf.project(xb, bv, 40, precision=prec, ckpt_every=10)
+    r64 = sf.project(xb.double(), bv.double(), 40, precision="fp64", fp_residual=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a.xi, b.xi) and torch.equal(a.lam, b.lam) and torch.equal(a.ckpt, b.ckpt)
+    assert torch.equal(a.resid[:, :2], b.resid)
+    e = ((a.resid[:, 2].double() - r64.resid[:, 2]).abs() / r64.resid[:, 2]).max().item()
+    _say(f"  fixed-point residual sum rel err {e:.2e}")
+    assert e <= (1e-4 if prec == "fp32" else 2e-3)
+
+
 @pytest.mark.parametrize("precision,n,tol", [("fp64", 40, 1e-8), ("fp32", 64, 2e-3)])
 def test_adjoint_at_its_size_limits(P, precision, n, tol):
     """The most robots the adjoint's LDS plan takes at degree 10 (FP64: 40 robots in 150 KB; FP32:

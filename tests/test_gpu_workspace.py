@@ -1,7 +1,7 @@
 """GPU parity of the workspace rows (the F_w block of eq. (f_e), eq. (workspace_polar)) against
 the FP64 oracle, through the C ABI: the generic kernel in FP64 and FP32, the MFMA kernels in FP32
 and the 16-bit forms, ragged batches that mix configs with and without a workspace, the
-violation report and the adjoint's refusal.
+violation report and the adjoint through the workspace rows.
 
 Tolerances as for the other constraints: FP64 elementwise |gpu - oracle| <= 1e-9 (1 + |oracle|);
 FP32 per sample max|gpu - oracle| / max|oracle| <= 1e-4; bf16 2e-3 and fp16 2e-4.
@@ -176,10 +176,36 @@ def test_violation_report_includes_workspace(P):
     assert (v[:, 4] == 0).all()
 
 
-def test_adjoint_refuses_workspace(P):
-    cfg, xb, bv = ws_problem(3, 2, 12, 7)
-    sf, out, bvd = run(P, cfg, xb, bv, 4, "fp32", ckpt_every=2)
-    with pytest.raises(P._native.SfError) as ei:
-        sf.project_backward(torch.as_tensor(xb, dtype=torch.float32).cuda(), bvd, 4, out.ckpt, 2,
-                            g_xi_out=torch.ones_like(out.xi))
-    assert ei.value.code == 4    # SF_EUNSUPPORTED
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 2e-3)])
+def test_adjoint_with_workspace_matches_oracle_autograd(P, prec, tol):
+    """The reverse mode through the workspace rows (their projection's 3x3 Jacobian, weight rho_ws)
+    and through their share of the final primal residual: gradients of ||xi^K - xi_bar||^2 +
+    ||r_p^K||^2 with respect to xi0, lambda0 and xi_bar against autograd through the oracle."""
+    cfg, xb, bv = ws_problem(4, 2, 20, 7)
+    rng = np.random.default_rng(9)
+    lam0 = rng.normal(size=xb.shape) * 0.1
+    iters, ce = 14, 5
+    s = O.build_system(cfg)
+    x0 = torch.tensor(xb, requires_grad=True)
+    l0 = torch.tensor(lam0, requires_grad=True)
+    xbo = torch.tensor(xb, requires_grad=True)
+    xk, _, r = O.sf_project(s, xbo, torch.tensor(bv), iters, xi0=x0, lam0=l0)
+    # the workspace is active in this case (some target differs from its position)
+    L = ((xk - torch.tensor(xb)) ** 2).sum() + r[:, 0].sum()
+    ref = torch.autograd.grad(L, (x0, l0, xbo))
+    _say(f"case adjoint with workspace {prec}")
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    sf = P.SafetyFilter([cfg])
+    xg = torch.tensor(xb, dtype=dt, device="cuda")
+    x0g = xg.clone().requires_grad_(True)
+    l0g = torch.tensor(lam0, dtype=dt, device="cuda").requires_grad_(True)
+    xbg = xg.clone().requires_grad_(True)
+    out = P.project_differentiable(sf, xbg, torch.tensor(bv, dtype=dt, device="cuda"), iters, xi0=x0g, lam0=l0g,
+                                   ckpt_every=ce, precision=prec)
+    Lg = ((out[0] - xg) ** 2).sum() + out[2].sum()
+    got = torch.autograd.grad(Lg, (x0g, l0g, xbg))
+    torch.cuda.synchronize()
+    for nm, a, b in zip(("xi0", "lam0", "xi_bar"), got, ref):
+        e = ((a.cpu().double() - b).abs().max() / b.abs().max()).item()
+        _say(f"  {nm}: rel err {e:.2e}")
+        assert e <= tol, (nm, e)
