@@ -116,6 +116,74 @@ __device__ void backproject_tile(const Ctx<T>& x, const T* tile, T* dst, int t0,
   }
 }
 
+// Final-residual term of the loss, g_resid ||r_p^K||^2 with r_p = F xi^K - e(F xi^{K-1}) (eq.
+// primal_residual), needs L.xprev = xi^{K-1} and L.g = xi^K: adds its cotangent of xi^K to gxi and
+// keeps the one of xi^{K-1} in pend (added after the reverse step of iteration K - 1).
+template <typename T>
+__device__ void resid_term(const Ctx<T>& x, const Lds<T>& L, T* Wt, T* GY, T* gxi, T* pend, T gres, int TT) {
+  const DevCfg& c = x.c;
+  const int n = x.n, D = x.D;
+  for (int t0 = 0; t0 < c.H; t0 += TT) {
+    const int TTc = min(TT, c.H - t0);
+    eval_tile<T>(c, x.basis, L.xprev, L.Y, t0, TTc, TT);
+    eval_tile<T>(c, x.basis, L.g, Wt, t0, TTc, TT);
+    __syncthreads();
+    for (int q = threadIdx.x; q < n * TTc; q += blockDim.x) {
+      const int i = q / TTc, tt = q - (q / TTc) * TTc;
+      T Ai[3] = {T(0), T(0), T(0)}, Bi[3] = {T(0), T(0), T(0)};
+      for (int j = 0; j < n; ++j) {
+        if (j == i) continue;
+        T rp[3], rn[3], R[3], gr[3], jt[3];
+        for (int d = 0; d < D; ++d) {
+          rp[d] = L.Y[(i * D + d) * TT + tt] - L.Y[(j * D + d) * TT + tt];
+          rn[d] = Wt[(i * D + d) * TT + tt] - Wt[(j * D + d) * TT + tt];
+        }
+        coll_resid<T>(rp, D, x.ia2, x.ib2, x.a, x.b, i < j, R);
+        for (int d = 0; d < D; ++d) gr[d] = T(2) * gres * (rn[d] - (rp[d] - R[d]));
+        coll_jt<T>(rp, gr, D, x.ia2, x.ib2, jt);
+        for (int d = 0; d < D; ++d) {
+          Ai[d] += gr[d];
+          Bi[d] += jt[d] - gr[d];
+        }
+      }
+      if (c.ws_on) {   // workspace rows: r_p = p_new - e(p_prev)
+        T v[3], R[3], gr[3], jt[3];
+        for (int d = 0; d < D; ++d) v[d] = L.Y[(i * D + d) * TT + tt];
+        ws_resid<T>(v, D, x.wc, x.ws_ia2, x.ws_ib2, R);
+        for (int d = 0; d < D; ++d) gr[d] = T(2) * gres * (Wt[(i * D + d) * TT + tt] - (v[d] - R[d]));
+        ws_jt<T>(v, gr, D, x.wc, x.ws_ia2, x.ws_ib2, jt);
+        for (int d = 0; d < D; ++d) {
+          Ai[d] += gr[d];
+          Bi[d] += jt[d] - gr[d];
+        }
+      }
+      for (int d = 0; d < D; ++d) {
+        GY[(i * D + d) * TT + tt] = Ai[d];
+        L.Rb[(i * D + d) * TT + tt] = Bi[d];
+      }
+      for (int bsel = 1; bsel < 3; ++bsel) {
+        const bool on = bsel == 1 ? c.vel_on : c.acc_on;
+        if (!on) continue;
+        const T lim = bsel == 1 ? x.vmax : x.amax;
+        T v[3], R[3], gr[3], jt[3];
+        for (int d = 0; d < D; ++d) v[d] = L.Y[((bsel * n + i) * D + d) * TT + tt];
+        ball_resid<T>(v, D, lim, R);
+        for (int d = 0; d < D; ++d)
+          gr[d] = T(2) * gres * (Wt[((bsel * n + i) * D + d) * TT + tt] - (v[d] - R[d]));
+        ball_jt<T>(v, gr, D, lim, jt);
+        for (int d = 0; d < D; ++d) {
+          GY[((bsel * n + i) * D + d) * TT + tt] = gr[d];
+          L.Rb[((bsel * n + i) * D + d) * TT + tt] = jt[d] - gr[d];
+        }
+      }
+    }
+    __syncthreads();
+    backproject_tile<T>(x, GY, gxi, t0, TTc, TT);
+    backproject_tile<T>(x, L.Rb, pend, t0, TTc, TT);
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 adjoint_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, const DevProblem* __restrict__ probs,
@@ -187,65 +255,7 @@ adjoint_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, const
             L.g[q] = xk[q];
           }
           __syncthreads();
-          for (int t0 = 0; t0 < c.H; t0 += TT) {
-            const int TTc = min(TT, c.H - t0);
-            eval_tile<T>(c, x.basis, L.xprev, L.Y, t0, TTc, TT);
-            eval_tile<T>(c, x.basis, L.g, Wt, t0, TTc, TT);
-            __syncthreads();
-            for (int q = threadIdx.x; q < n * TTc; q += blockDim.x) {
-              const int i = q / TTc, tt = q - (q / TTc) * TTc;
-              T Ai[3] = {T(0), T(0), T(0)}, Bi[3] = {T(0), T(0), T(0)};
-              for (int j = 0; j < n; ++j) {
-                if (j == i) continue;
-                T rp[3], rn[3], R[3], gr[3], jt[3];
-                for (int d = 0; d < D; ++d) {
-                  rp[d] = L.Y[(i * D + d) * TT + tt] - L.Y[(j * D + d) * TT + tt];
-                  rn[d] = Wt[(i * D + d) * TT + tt] - Wt[(j * D + d) * TT + tt];
-                }
-                coll_resid<T>(rp, D, x.ia2, x.ib2, x.a, x.b, i < j, R);
-                for (int d = 0; d < D; ++d) gr[d] = T(2) * gres * (rn[d] - (rp[d] - R[d]));
-                coll_jt<T>(rp, gr, D, x.ia2, x.ib2, jt);
-                for (int d = 0; d < D; ++d) {
-                  Ai[d] += gr[d];
-                  Bi[d] += jt[d] - gr[d];
-                }
-              }
-              if (c.ws_on) {   // workspace rows: r_p = p_new - e(p_prev)
-                T v[3], R[3], gr[3], jt[3];
-                for (int d = 0; d < D; ++d) v[d] = L.Y[(i * D + d) * TT + tt];
-                ws_resid<T>(v, D, x.wc, x.ws_ia2, x.ws_ib2, R);
-                for (int d = 0; d < D; ++d) gr[d] = T(2) * gres * (Wt[(i * D + d) * TT + tt] - (v[d] - R[d]));
-                ws_jt<T>(v, gr, D, x.wc, x.ws_ia2, x.ws_ib2, jt);
-                for (int d = 0; d < D; ++d) {
-                  Ai[d] += gr[d];
-                  Bi[d] += jt[d] - gr[d];
-                }
-              }
-              for (int d = 0; d < D; ++d) {
-                GY[(i * D + d) * TT + tt] = Ai[d];
-                L.Rb[(i * D + d) * TT + tt] = Bi[d];
-              }
-              for (int bsel = 1; bsel < 3; ++bsel) {
-                const bool on = bsel == 1 ? c.vel_on : c.acc_on;
-                if (!on) continue;
-                const T lim = bsel == 1 ? x.vmax : x.amax;
-                T v[3], R[3], gr[3], jt[3];
-                for (int d = 0; d < D; ++d) v[d] = L.Y[((bsel * n + i) * D + d) * TT + tt];
-                ball_resid<T>(v, D, lim, R);
-                for (int d = 0; d < D; ++d)
-                  gr[d] = T(2) * gres * (Wt[((bsel * n + i) * D + d) * TT + tt] - (v[d] - R[d]));
-                ball_jt<T>(v, gr, D, lim, jt);
-                for (int d = 0; d < D; ++d) {
-                  GY[((bsel * n + i) * D + d) * TT + tt] = gr[d];
-                  L.Rb[((bsel * n + i) * D + d) * TT + tt] = jt[d] - gr[d];
-                }
-              }
-            }
-            __syncthreads();
-            backproject_tile<T>(x, GY, gxi, t0, TTc, TT);
-            backproject_tile<T>(x, L.Rb, pend, t0, TTc, TT);
-            __syncthreads();
-          }
+          resid_term<T>(x, L, Wt, GY, gxi, pend, gres, TT);
         }
         // reverse sweep over the segment
         for (int k = s1 - 1; k >= s0; --k) {
@@ -379,9 +389,67 @@ adjoint_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, const
   }
 }
 
+// The final-residual term for the MFMA adjoint path: per sample, from the recomputed states
+// xi^{K-1} (slot `slot` of `states`) and xi^K (slot `slot` + 1), slots 2 * stride elements apart,
+// it initialises the carried cotangents (gxi = g_xi_out + the term's cotangent of xi^K, glam =
+// g_lam_out, gxb = 0; each [stride] in `carry`) and writes pend (the cotangent of xi^{K-1}).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+adjoint_resid_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, const DevProblem* __restrict__ probs,
+                     const WorkItem* __restrict__ items, int n_items, const T* __restrict__ states, int64_t stride,
+                     int slot, const T* __restrict__ g_xi_out, const T* __restrict__ g_lam_out,
+                     const T* __restrict__ g_resid, T* __restrict__ carry, T* __restrict__ pend, int TT) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const WorkItem w = items[it];
+    const DevProblem pr = probs[w.problem];
+    const Ctx<T> x = make_ctx<T>(cfgs[pr.cfg], tab);
+    const Lds<T> L = carve<T>(smem, lds_plan(x.c, TT));
+    const AdjPlan A = adj_plan(x.c, TT);
+    T* gxi = smem + A.gxi;
+    T* pd = smem + A.pend;
+    const int nDm = x.nDm;
+    for (int sl = w.first; sl < w.first + w.count; ++sl) {
+      const int64_t coef = pr.coef_off + (int64_t)sl * nDm;
+      const T gres = g_resid[pr.sample_base + sl];
+      const T* xk1 = states + (int64_t)slot * 2 * stride + coef;
+      const T* xk = xk1 + 2 * stride;
+      for (int q = threadIdx.x; q < nDm; q += blockDim.x) {
+        L.xprev[q] = xk1[q];
+        L.g[q] = xk[q];
+        gxi[q] = g_xi_out ? g_xi_out[coef + q] : T(0);
+        pd[q] = T(0);
+      }
+      __syncthreads();
+      if (gres != T(0)) resid_term<T>(x, L, smem + A.W, smem + A.GY, gxi, pd, gres, TT);
+      for (int q = threadIdx.x; q < nDm; q += blockDim.x) {
+        carry[coef + q] = gxi[q];
+        carry[stride + coef + q] = g_lam_out ? g_lam_out[coef + q] : T(0);
+        carry[2 * stride + coef + q] = T(0);
+        pend[coef + q] = pd[q];
+      }
+      __syncthreads();
+    }
+  }
+}
+
 }  // namespace
 
 size_t adjoint_lds_bytes(const DevCfg& c, int tile, size_t elem) { return adj_plan(c, tile).total * elem; }
+
+hipError_t launch_adjoint_resid(const AdjointArgs& a, const float* states, int64_t stride, int slot, float* carry,
+                                float* pend) {
+  auto kern = adjoint_resid_kernel<float>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(a.n_items), dim3(kBlock), a.lds_bytes, a.stream, a.cfgs,
+                     static_cast<const float*>(a.tab), a.probs, a.items, a.n_items, states, stride, slot,
+                     static_cast<const float*>(a.g_xi_out), static_cast<const float*>(a.g_lam_out),
+                     static_cast<const float*>(a.g_resid), carry, pend, a.tile);
+  return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_adjoint(const AdjointArgs& a) {

@@ -545,6 +545,104 @@ sf_status get_eq_chunks(sf_handle h, Plan* p) {
   return SF_OK;
 }
 
+// Reverse mode on the matrix cores (fp32; batches the MFMA forward kernels cover, up to 16 robots,
+// no workspace rows).  Per checkpoint segment, last first: the forward MFMA kernel recomputes the
+// segment's states from its checkpoint (with checkpoints every iteration into the scratch), the
+// final-residual term is formed once from the last two states, and the reverse sweep carries the
+// cotangents of (xi, lambda, xi_bar) to the segment's start.
+sf_status adjoint_fast_path(sf_handle h, Plan* p, int32_t precision, const void* xi_bar, const void* bvals,
+                            int32_t iters, const float* ckpt, int32_t ckpt_every, const void* g_xi_out,
+                            const void* g_lam_out, const void* g_resid, const void* w_fpr, void* g_xi0, void* g_lam0,
+                            void* g_xi_bar, void* stream) {
+  const int64_t stride = p->total_coef;
+  const size_t need = ((size_t)2 * (ckpt_every + 1) + 4) * stride * sizeof(float);   // states, carries, pend
+  if (need > h->scratch_bytes) {
+    if (h->scratch) (void)hipFree(h->scratch);
+    h->scratch = nullptr;
+    h->scratch_bytes = 0;
+    if (hipMalloc(&h->scratch, need) != hipSuccess) return fail(SF_ENOMEM, "adjoint scratch allocation failed");
+    h->scratch_bytes = need;
+  }
+  float* states = static_cast<float*>(h->scratch);
+  float* carry = states + (size_t)2 * (ckpt_every + 1) * stride;
+  float* pend = carry + 3 * stride;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  size_t lds = 0;
+  for (int32_t sl : p->slots_used) lds = std::max(lds, sf::adjoint_fast_lds_bytes(h->cfgs[sl].dev));
+  const int nseg = (iters + ckpt_every - 1) / ckpt_every;
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int s0 = seg * ckpt_every, len = std::min(ckpt_every, iters - s0);
+    sf::LaunchArgs la{};
+    la.cfgs = h->d_cfgs;
+    la.probs = p->d_probs;
+    la.items = p->d_items;
+    la.n_items = p->n_items;
+    la.xi_bar = xi_bar;
+    la.bvals = bvals;
+    la.xi0 = ckpt + (size_t)seg * 2 * stride;
+    la.lam0 = ckpt + (size_t)seg * 2 * stride + stride;
+    la.iters = len;
+    la.xi_out = states + (size_t)len * 2 * stride;
+    la.lam_out = states + (size_t)len * 2 * stride + stride;
+    la.ckpt = states;
+    la.ckpt_every = 1;
+    la.ckpt_stride = stride;
+    la.stream = s;
+    hipError_t e = sf::fast_launch(p->fast, la, h->d_tab32, h->d_a16, precision);
+    if (e != hipSuccess) return hip_fail(e, "sf_project_backward recompute");
+    bool init = false;
+    const float* pendp = nullptr;
+    if (seg == nseg - 1) {
+      if (g_resid) {
+        sf::AdjointArgs ra{};
+        ra.cfgs = h->d_cfgs;
+        ra.tab = h->d_tab32;
+        ra.probs = p->d_probs;
+        ra.items = p->d_items;
+        ra.n_items = p->n_items;
+        ra.g_xi_out = g_xi_out;
+        ra.g_lam_out = g_lam_out;
+        ra.g_resid = g_resid;
+        ra.stream = s;
+        sf_status st = pick_tile(h, p, sizeof(float), adj_bytes, &ra.tile, &ra.lds_bytes);
+        if (st != SF_OK) return st;
+        e = sf::launch_adjoint_resid(ra, states, stride, len - 1, carry, pend);
+        if (e != hipSuccess) return hip_fail(e, "sf_project_backward final-residual term");
+        pendp = pend;
+      } else {
+        init = true;
+      }
+    }
+    sf::AdjFastArgs f{};
+    f.cfgs = h->d_cfgs;
+    f.tab = h->d_tab32;
+    f.a32 = h->d_a16;
+    f.probs = p->d_probs;
+    f.items = p->d_items;
+    f.n_items = p->n_items;
+    f.states = states;
+    f.stride = stride;
+    f.s0 = s0;
+    f.len = len;
+    f.iters = iters;
+    f.w_fpr = static_cast<const float*>(w_fpr);
+    f.g_xi_out = static_cast<const float*>(g_xi_out);
+    f.g_lam_out = static_cast<const float*>(g_lam_out);
+    f.init = init;
+    f.carry = carry;
+    f.pend = pendp;
+    f.last = seg == 0;
+    f.g_xi0 = static_cast<float*>(g_xi0);
+    f.g_lam0 = static_cast<float*>(g_lam0);
+    f.g_xi_bar = static_cast<float*>(g_xi_bar);
+    f.lds_bytes = lds;
+    f.stream = s;
+    e = sf::launch_adjoint_fast(f, p->fast.KS);
+    if (e != hipSuccess) return hip_fail(e, "sf_project_backward reverse sweep");
+  }
+  return SF_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------
@@ -799,10 +897,14 @@ sf_status sf_project_backward(sf_handle h, const sf_batch* batch, int32_t precis
   st = get_plan(h, batch, &p);
   if (st != SF_OK) return st;
   int64_t max_ndm = 0;
+  bool fast = precision != SF_FP64 && iters > 0 && p->fast.ok && !(p->fast.ws);
   for (int32_t s : p->slots_used) {
     const sf::DevCfg& c = h->cfgs[s].dev;
     max_ndm = std::max<int64_t>(max_ndm, (int64_t)c.n * c.D * c.m);
+    fast = fast && sf::adjoint_fast_supported(c);
   }
+  if (fast) return adjoint_fast_path(h, p, precision, xi_bar, bvals, iters, static_cast<const float*>(ckpt), ckpt_every,
+                                     g_xi_out, g_lam_out, g_resid, w_fpr, g_xi0, g_lam0, g_xi_bar, stream);
   sf::AdjointArgs a{};
   a.state_stride = (int64_t)2 * (ckpt_every + 1) * max_ndm;   // xi and lambda states of a segment
   const size_t need = (size_t)p->n_items * a.state_stride * elem;

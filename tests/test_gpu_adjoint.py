@@ -206,6 +206,86 @@ def test_fixed_point_residual_sum_on_the_mfma_kernel(P, prec):
     assert e <= (1e-4 if prec == "fp32" else 2e-3)
 
 
+def oracle_chained(cfg, xi_bar, b, xi0, lam0, iters, w):
+    """Autograd through the oracle's iterations taken one at a time, with the loss
+    w sum_k ||z^{k+1} - z^k||^2 + ||xi^K - xi_bar||^2 + ||r_p^K||^2."""
+    s = O.build_system(cfg)
+    xb = torch.tensor(xi_bar, requires_grad=True)
+    x0 = torch.tensor(xi0, requires_grad=True)
+    l0 = torch.tensor(lam0, requires_grad=True)
+    xi, lam = x0, l0
+    fsum = torch.zeros(xi_bar.shape[0], dtype=torch.float64)
+    r = None
+    for _ in range(iters):
+        xn, ln, r = O.sf_project(s, xb, torch.tensor(b), 1, xi0=xi, lam0=lam)
+        fsum = fsum + ((xn - xi) ** 2).sum((1, 2, 3)) + ((ln - lam) ** 2).sum((1, 2, 3))
+        xi, lam = xn, ln
+    L = w * fsum.sum() + ((xi - torch.tensor(xi_bar)) ** 2).sum() + r[:, 0].sum()
+    return torch.autograd.grad(L, (x0, l0, xb))
+
+
+@pytest.mark.parametrize("n,H,degree,iters,ce,prec", [(6, 30, 8, 17, 5, "fp32"), (16, 100, 10, 20, 10, "fp32"),
+                                                      (16, 100, 10, 20, 10, "bf16"), (11, 45, 13, 9, 4, "fp32")])
+def test_mfma_adjoint_matches_oracle_autograd(P, n, H, degree, iters, ce, prec):
+    """The reverse mode on the matrix cores (recompute with the forward MFMA kernel, reverse sweep
+    per checkpoint segment) with every loss term: the projected coefficients, the final residual
+    and the fixed-point residual sum, against autograd through the oracle; segments that do not
+    divide the iterations, degrees 8 to 13 and the bf16 forward."""
+    cfg, xi, b, rng = problem(n=n, S=3, H=H, degree=degree, seed=40 + n, box=2.0 if n > 8 else 1.0, T=8.0)
+    xi0 = xi + rng.normal(size=xi.shape) * 0.05
+    lam0 = rng.normal(size=xi.shape) * 0.1
+    w = 0.3
+    ref = oracle_chained(cfg, xi, b, xi0, lam0, iters, w)
+    _say(f"case MFMA adjoint n={n} H={H} degree={degree} iters={iters} ckpt_every={ce} {prec}")
+    sf = P.SafetyFilter([cfg])
+    dt = torch.float32
+    xbg = torch.tensor(xi, dtype=dt, device="cuda").requires_grad_(True)
+    x0g = torch.tensor(xi0, dtype=dt, device="cuda").requires_grad_(True)
+    l0g = torch.tensor(lam0, dtype=dt, device="cuda").requires_grad_(True)
+    xk, _, res, fpr = P.project_differentiable(sf, xbg, torch.tensor(b, dtype=dt, device="cuda"), iters, xi0=x0g,
+                                               lam0=l0g, ckpt_every=ce, precision=prec)
+    L = w * fpr.sum() + ((xk - xbg.detach()) ** 2).sum() + res.sum()
+    got = torch.autograd.grad(L, (x0g, l0g, xbg))
+    torch.cuda.synchronize()
+    tol = 2e-3 if prec == "fp32" else 1e-2
+    for nm, a, r in zip(("xi0", "lam0", "xi_bar"), got, ref):
+        e = rel_err(a.cpu().double(), r)
+        _say(f"  {nm}: rel err {e:.2e}")
+        assert e <= tol, (nm, e)
+
+
+def test_mfma_adjoint_ragged_batch_equals_per_problem(P):
+    """A batch of two swarm sizes through the MFMA adjoint equals per-problem calls."""
+    probs = [problem(n=n, S=S, H=40, degree=9, seed=60 + n, box=1.5) for n, S in ((5, 3), (12, 2))]
+    cfgs = [p[0] for p in probs]
+    sf = P.SafetyFilter(cfgs)
+    batch = P.Batch([(0, 3), (1, 2)])
+    xb = torch.cat([torch.tensor(p[1], dtype=torch.float32).reshape(-1) for p in probs]).cuda()
+    bv = torch.cat([torch.tensor(p[2], dtype=torch.float32).reshape(-1) for p in probs]).cuda()
+    iters, ce = 12, 5
+    _say("case MFMA adjoint ragged batch")
+    out = sf.project(xb, bv, iters, batch=batch, ckpt_every=ce, fp_residual=True)
+    g_xi = torch.ones_like(xb)
+    g_res = torch.ones((5,), dtype=torch.float32, device="cuda")
+    w = torch.full((5,), 0.5, dtype=torch.float32, device="cuda")
+    g = sf.project_backward(xb, bv, iters, out.ckpt, ce, g_xi_out=g_xi, g_resid=g_res, w_fpr=w, batch=batch)
+    torch.cuda.synchronize()
+    o = r0 = 0
+    for k, (cfg, xi, b, _) in enumerate(probs):
+        one = P.SafetyFilter([cfg])
+        x1 = torch.tensor(xi, dtype=torch.float32).cuda()
+        b1 = torch.tensor(b, dtype=torch.float32).cuda()
+        o1 = one.project(x1, b1, iters, ckpt_every=ce, fp_residual=True)
+        S = xi.shape[0]
+        g1 = one.project_backward(x1, b1, iters, o1.ckpt, ce, g_xi_out=torch.ones_like(x1),
+                                  g_resid=g_res[r0:r0 + S].contiguous(), w_fpr=w[r0:r0 + S].contiguous())
+        torch.cuda.synchronize()
+        for key in ("xi0", "lam0", "xi_bar"):
+            assert torch.allclose(g[key][o:o + xi.size].reshape(g1[key].shape), g1[key], rtol=1e-5, atol=1e-6), key
+        o += xi.size
+        r0 += S
+
+
 @pytest.mark.parametrize("precision,n,tol", [("fp64", 40, 1e-8), ("fp32", 64, 2e-3)])
 def test_adjoint_at_its_size_limits(P, precision, n, tol):
     """The most robots the adjoint's LDS plan takes at degree 10 (FP64: 40 robots in 150 KB; FP32:
