@@ -15,8 +15,8 @@ OBJDIR = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libswarmsf.so")
 # the MFMA kernel instances are compiled per operand precision and workspace flag, in parallel
 FAST_INSTANCES = [f"sf_fast_p{mp}_w{ws}.hip" for mp in range(3) for ws in range(2)]
-SOURCES = FAST_INSTANCES + ["sf_fast.hip", "sf_api.hip", "sf_generic.hip", "sf_adjoint.hip", "sf_adjoint_fast.hip",
-                            "sf_eqqp.hip"]
+SOURCES = FAST_INSTANCES + ["sf_fast.hip", "sf_api.hip", "sf_generic.hip", "sf_status.hip", "sf_adjoint.hip",
+                            "sf_adjoint_fast.hip", "sf_eqqp.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

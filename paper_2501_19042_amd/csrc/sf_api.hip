@@ -473,6 +473,7 @@ sf_status autotune(sf_handle h, const Plan* p, sf::FastPlan& fp, const sf::Launc
   // over large ragged batches the best of two 30-iteration runs
   sf::LaunchArgs t = a;
   t.iters = std::max(1, std::min(a.iters, fp.batched ? 30 : 50));
+  t.status_out = nullptr;   // trial launches read and write no status
   const int warm = fp.batched ? 1 : 2, reps = fp.batched ? 2 : 3;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(SF_EDEVICE, "events");
@@ -822,9 +823,8 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
     st = autotune(h, p, *fp, a, precision);
     if (st != SF_OK) return st;
   }
-  auto launch = [&](hipStream_t s) -> hipError_t {
-    sf::LaunchArgs b = a;
-    b.stream = s;
+  auto solve = [&](const sf::LaunchArgs& b0) -> hipError_t {
+    sf::LaunchArgs b = b0;
     if (fp) return sf::fast_launch(*fp, b, h->d_tab32, h->d_a16, precision);
     if (precision == SF_FP64) {
       b.tab = h->d_tab64;
@@ -832,6 +832,16 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
     }
     b.tab = h->d_tab32;
     return sf::launch_generic_project<float>(b);
+  };
+  // with status_out: input check before the solve, finiteness of the outputs after it
+  auto launch = [&](hipStream_t s) -> hipError_t {
+    sf::LaunchArgs b = a;
+    b.stream = s;
+    hipError_t le = hipSuccess;
+    if (status_out) le = sf::launch_status_input(b, precision == SF_FP64);
+    if (le == hipSuccess) le = solve(b);
+    if (le == hipSuccess && status_out) le = sf::launch_status_output(b, precision == SF_FP64);
+    return le;
   };
   hipError_t e;
   if (flags & SF_USE_GRAPH) {

@@ -134,7 +134,7 @@ __host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W, 
   const int NT = (c.H + 15) / 16, TQ = (NT + W - 1) / W;
   int pw = p.plist + TQ * (Npmax + 1);
   if (pw < nDm) pw = nDm;
-  if (pw < 192) pw = 192;
+  if (pw < 128) pw = 128;
   p.per_wave = (pw + 3) & ~3;
   p.tiles = o;
   o += W * p.per_wave;
@@ -181,6 +181,13 @@ __device__ __forceinline__ float group_sum(float v) {
     v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
   }
   return v;
+}
+
+// Sum over the 64 lanes of a wave (all lanes active; every lane gets the same value).
+__device__ __forceinline__ float wave_sum(float v) {
+  v = group_sum<32>(v);
+  const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(a[0]) + __uint_as_float(a[1]);
 }
 
 // Maximum over the 64 lanes of a wave (all lanes active; every lane gets the result).
@@ -356,39 +363,19 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
       const int col = lane & 15, grp = lane >> 4;
       const int64_t coef = pr.coef_off + (int64_t)sl * nDm;
       const int64_t sidx = pr.sample_base + sl;
-      int bad = 0;   // a NaN or infinite input: the sample is not iterated, its outputs are NaN
       for (int q = tid; q < nDm; q += nthr) {
         const float x = xi_bar[coef + q];
-        const float x0 = xi0 ? xi0[coef + q] : x;
-        const float l0 = lam0 ? lam0[coef + q] : 0.0f;
         sxb[q] = x;
-        sxi[q] = x0;
-        slam[q] = l0;
-        bad |= nonfinite_bits(x) | nonfinite_bits(x0) | nonfinite_bits(l0);
+        sxi[q] = xi0 ? xi0[coef + q] : x;
+        slam[q] = lam0 ? lam0[coef + q] : 0.0f;
       }
-      for (int q = tid; q < 3 * n * kNFix; q += nthr) bad |= nonfinite_bits(bv[q]);
       for (int q = tid; q < 3 * NR; q += nthr) s_dxi[q] = 0.0f;
       for (int q = lane; q < 3 * NR * 16; q += 64) Ct[q] = 0.0f;
-      if (__syncthreads_or(bad)) {
-        const float qnan = quiet_nan_f32();
-        for (int q = tid; q < nDm; q += nthr) {
-          xi_out[coef + q] = qnan;
-          if (lam_out) lam_out[coef + q] = qnan;
-          if (ckpt)
-            for (int k = 0; k < iters; k += ckpt_every) {
-              const int64_t base = (int64_t)(k / ckpt_every) * 2 * ckpt_stride + coef;
-              ckpt[base + q] = qnan;
-              ckpt[base + ckpt_stride + q] = qnan;
-            }
-        }
-        if (tid == 0) {
-          if (resid_out)
-            for (int c = 0; c < rw; ++c) resid_out[sidx * rw + c] = qnan;
-          if (status_out) status_out[sidx] = SF_SAMPLE_NONFINITE_INPUT;
-        }
-        __syncthreads();
-        continue;
-      }
+      // a sample the input check flagged (non-finite input) is not iterated; the status pass then
+      // writes NaN over its outputs
+      const int32_t in_flag = status_out ? __builtin_amdgcn_readfirstlane(status_out[sidx]) : 0;
+      const int iters_s = in_flag < 0 ? 0 : iters;
+      __syncthreads();
       // per-row bound on |coefficient| over the iterates: the initial one and the pinned values
       for (int q = tid; q < 3 * NR; q += nthr) {
         float cm = 0.0f;
@@ -442,7 +429,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
       float fpsum = 0.0f;
       const float skx = (float)(c.skin * c.a) * 0.999f, skz = (float)(c.skin * c.b) * 0.999f;
 
-      for (int k = 0; k < iters; ++k) {
+      for (int k = 0; k < iters_s; ++k) {
         // Lane-dependent indices are re-derived from an opaque copy every iteration: otherwise the
         // compiler hoists every per-lane address of the loop body out of the sample loop and
         // spills them.
@@ -457,7 +444,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             ckpt[base + ckpt_stride + q] = slam[q];
           }
         }
-        if ((resid_out || status_out) && k == iters - 1)
+        if ((resid_out || status_out) && k == iters_s - 1)
           for (int q = tid; q < nDm; q += nthr) sxprev[q] = sxi[q];
         // Velocity/acceleration at every grid time move by at most L * ||max_k |d xi_{i,d,k}| ||_2
         // per step (L = max_t sum_k |basis row|).  While the accumulated drift of every robot stays
@@ -1015,7 +1002,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
       float rmax = 0.0f;   // its largest block norm (thread 0)
       if (resid_out || status_out) {
         float ss = 0.0f, mx = 0.0f;
-        if (iters > 0) {
+        if (iters_s > 0) {
           // One basis product of a tile for the iterate in `src` (previous or new).  The B operands
           // are formed per product (this runs once per solve), so that only one iterate's
           // products are live at a time.
@@ -1150,20 +1137,24 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             wave_sync();
           }
         }
-        // per-wave partial sums in the wave's own region, combined in thread order
-        wbuf[lane] = ss;
-        wbuf[64 + lane] = mx;
-        wbuf[128 + lane] = fpsum;
+        // per-wave sums and maxima (cross-lane, in a fixed order) in the wave's own region, then
+        // combined in wave order
+        {
+          const float ws = wave_sum(ss), wm = wave_max(mx), wf = wave_sum(fpsum);
+          if (lane == 0) {
+            wbuf[0] = ws;
+            wbuf[1] = wm;
+            wbuf[2] = wf;
+          }
+        }
         __syncthreads();
         if (tid == 0) {
           float s = 0.0f, mm = 0.0f, fs = 0.0f;
           for (int ww = 0; ww < W; ++ww) {
             const float* pw = smem + L.tiles + ww * L.per_wave;
-            for (int l = 0; l < 64; ++l) {
-              s += pw[l];
-              mm = fmaxf(mm, pw[64 + l]);
-              fs += pw[128 + l];
-            }
+            s += pw[0];
+            mm = fmaxf(mm, pw[1]);
+            fs += pw[2];
           }
           rmax = sqrtf(mm);
           if (resid_out) {
@@ -1174,14 +1165,13 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         }
         __syncthreads();
       }
-      int bad_out = 0;
       for (int q = tid; q < nDm; q += nthr) {
         xi_out[coef + q] = sxi[q];
         if (lam_out) lam_out[coef + q] = slam[q];
-        bad_out |= nonfinite_bits(sxi[q]) | nonfinite_bits(slam[q]);
       }
-      bad_out = __syncthreads_or(bad_out);
-      if (status_out && tid == 0) status_out[sidx] = sample_status<float>(false, bad_out != 0, rmax, iters);
+      // convergence bits (the status pass adds the finiteness of the outputs)
+      if (status_out && tid == 0) status_out[sidx] = in_flag < 0 ? in_flag : sample_status<float>(false, false, rmax, iters_s);
+      __syncthreads();
     }
   }
 }

@@ -50,35 +50,14 @@ generic_project_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ ta
       const int64_t sidx = pr.sample_base + sl;
       setup_sample<T>(x, L, xi_bar + coef, bvals + pr.bnd_off, xi0 ? xi0 + coef : nullptr,
                       lam0 ? lam0 + coef : nullptr);
-      // a sample with a NaN or infinite input is not iterated: its outputs are NaN
-      int bad = 0;
-      for (int q = threadIdx.x; q < nDm; q += blockDim.x)
-        bad |= nonfinite_bits(L.xb[q]) | nonfinite_bits(L.xi[q]) | nonfinite_bits(L.lam[q]);
-      for (int q = threadIdx.x; q < x.nD6; q += blockDim.x) bad |= nonfinite_bits(bvals[pr.bnd_off + q]);
-      if (__syncthreads_or(bad)) {
-        const T qnan = sizeof(T) == 8 ? T(quiet_nan_f64()) : T(quiet_nan_f32());
-        for (int q = threadIdx.x; q < nDm; q += blockDim.x) {
-          xi_out[coef + q] = qnan;
-          if (lam_out) lam_out[coef + q] = qnan;
-          if (ckpt)
-            for (int k = 0; k < iters; k += ckpt_every) {
-              const int64_t base = (int64_t)(k / ckpt_every) * 2 * ckpt_stride + coef;
-              ckpt[base + q] = qnan;
-              ckpt[base + ckpt_stride + q] = qnan;
-            }
-        }
-        if (resid_out) {
-          const int64_t nr = history ? (int64_t)iters * 2 : rw;
-          for (int64_t q = threadIdx.x; q < nr; q += blockDim.x) resid_out[sidx * nr + q] = qnan;
-        }
-        if (status_out && threadIdx.x == 0) status_out[sidx] = SF_SAMPLE_NONFINITE_INPUT;
-        __syncthreads();
-        continue;
-      }
+      // a sample the input check flagged (non-finite input) is not iterated; the status pass then
+      // writes NaN over its outputs
+      const int32_t in_flag = status_out ? status_out[sidx] : 0;
+      const int iters_s = in_flag < 0 ? 0 : iters;
       const bool final_resid = (resid_out || status_out) && !(history && resid_out);
       T last_mx = T(0);   // largest block norm of the last residual in history mode
       T fsum = T(0);   // this thread's share of the fixed-point residual sum
-      for (int k = 0; k < iters; ++k) {
+      for (int k = 0; k < iters_s; ++k) {
         if (ckpt && (k % ckpt_every) == 0) {
           const int64_t base = (int64_t)(k / ckpt_every) * 2 * ckpt_stride + coef;
           for (int q = threadIdx.x; q < nDm; q += blockDim.x) {
@@ -86,7 +65,7 @@ generic_project_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ ta
             ckpt[base + ckpt_stride + q] = L.lam[q];
           }
         }
-        if (history || fpr || (final_resid && k == iters - 1))
+        if (history || fpr || (final_resid && k == iters_s - 1))
           for (int q = threadIdx.x; q < nDm; q += blockDim.x) L.xprev[q] = L.xi[q];
         iteration<T>(x, L, TT, k);
         if (fpr) {
@@ -110,7 +89,7 @@ generic_project_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ ta
       }
       if (final_resid) {
         T ss = T(0), mx = T(0);
-        if (iters > 0) residual_pass<T>(x.c, x.basis, L, TT, ss, mx);
+        if (iters_s > 0) residual_pass<T>(x.c, x.basis, L, TT, ss, mx);
         if (fpr) {
           T unused = T(0);
           block_reduce_sum_max<T>(L.red, fsum, unused);
@@ -122,14 +101,14 @@ generic_project_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ ta
         }
         last_mx = mx;
       }
-      int bad_out = 0;
       for (int q = threadIdx.x; q < nDm; q += blockDim.x) {
         xi_out[coef + q] = L.xi[q];
         if (lam_out) lam_out[coef + q] = L.lam[q];
-        bad_out |= nonfinite_bits(L.xi[q]) | nonfinite_bits(L.lam[q]);
       }
-      bad_out = __syncthreads_or(bad_out);
-      if (status_out && threadIdx.x == 0) status_out[sidx] = sample_status<T>(false, bad_out != 0, last_mx, iters);
+      // convergence bits (the status pass adds the finiteness of the outputs)
+      if (status_out && threadIdx.x == 0)
+        status_out[sidx] = in_flag < 0 ? in_flag : sample_status<T>(false, false, last_mx, iters_s);
+      __syncthreads();
     }
   }
 }

@@ -115,6 +115,14 @@ __host__ __device__ inline int32_t sample_status(bool bad_input, bool bad_output
   return s;
 }
 
+// Status passes of sf_project (with status_out): before the solve, samples with a non-finite input
+// get kStatusInputFlag (negative, so the solve kernels recognise it and skip the sample) and the
+// others 0; the solve kernels write the convergence bits; after the solve, flagged samples get NaN
+// outputs and SF_SAMPLE_NONFINITE_INPUT, the others SF_SAMPLE_NONFINITE if an output is not finite.
+constexpr int32_t kStatusInputFlag = (int32_t)0x80000001u;
+hipError_t launch_status_input(const LaunchArgs& a, bool dbl);
+hipError_t launch_status_output(const LaunchArgs& a, bool dbl);
+
 // Generic fused kernels (any shape that fits the LDS plan), T = double or float.
 template <typename T>
 hipError_t launch_generic_project(const LaunchArgs& a);
