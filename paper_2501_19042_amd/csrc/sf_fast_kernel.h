@@ -267,6 +267,11 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
   constexpr int FHP = (FH + 3) & ~3;                  // ... padded to whole 16-byte chunks
   static_assert(HALVES * FHP <= kQPCols, "QP matrix rows");
   constexpr int TAILW = (3 * NR * HALVES + 63) / 64;  // waves running the multiplier and QP steps
+  // One robot tile and three waves: wave a runs axis a of the multiplier/QP step with four lanes per
+  // row (robot, a), so every wave shares it.
+  constexpr bool QUART = R == 1 && W == 3;
+  constexpr int FQ = (MFX + 3) / 4;                   // free coefficients per lane in that layout
+  constexpr int QC = (MFX + 3) / 4;                   // 16-byte chunks of a QP matrix row
   static_assert(TAILW <= W, "the multiplier/QP step needs 3 x 16R lanes");
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nthr = 64 * W;
@@ -341,10 +346,18 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
     // into the halves of the outputs the lanes own: [matrix][half][f2][j] = X[half * FH + j][f2]
     // (zero-padded)
     float* sX1 = smem + L.qp;
-    for (int q = tid; q < 2 * HALVES * mf * FHP; q += nthr) {
-      const int j = q % FHP, f2 = (q / FHP) % mf, mh = q / (FHP * mf);
-      const int h = mh % HALVES, mat = mh / HALVES, f = h * FH + j;
-      sX1[q] = (j < FH && f < mf) ? (mat == 0 ? X1 : X01)[f * mf + f2] : 0.0f;
+    if constexpr (QUART) {
+      // [matrix][f][f2], rows of 4 QC floats (zero-padded)
+      for (int q = tid; q < 2 * mf * 4 * QC; q += nthr) {
+        const int c4 = q % (4 * QC), f = (q / (4 * QC)) % mf, mat = q / (4 * QC * mf);
+        sX1[q] = c4 < mf ? (mat == 0 ? X1 : X01)[f * mf + c4] : 0.0f;
+      }
+    } else {
+      for (int q = tid; q < 2 * HALVES * mf * FHP; q += nthr) {
+        const int j = q % FHP, f2 = (q / FHP) % mf, mh = q / (FHP * mf);
+        const int h = mh % HALVES, mat = mh / HALVES, f = h * FH + j;
+        sX1[q] = (j < FH && f < mf) ? (mat == 0 ? X1 : X01)[f * mf + f2] : 0.0f;
+      }
     }
     // basis operand tables: fp32 [tile][basis][S1 A operand, S4 B operand (x rho)][lane],
     // 16-bit [tile][basis][instruction][lane]
@@ -630,7 +643,9 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           }
           bool ws_nz = false;   // some workspace residual of the tile is nonzero (wave-uniform)
           // ---- S1 positions -> LDS, per-robot boxes over the tile in registers ----
-          {
+          // (not needed when the tile's kept pair list is empty and no list or workspace row is
+          // evaluated: then no residual of the tile is nonzero)
+          if (rebuild || __builtin_amdgcn_readfirstlane(kept_count) > 0 || (WS && ws_eval)) {
             f4 Y[R][3];
             if constexpr (MP == 0) s1_32(ca, Y);
             else s1_16(cu1, cu2, Y);
@@ -809,7 +824,12 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         }
         // this wave's partial back-projection and bound maxima -> its own LDS region
         {
+          // Every lane stores, without branches: the rows of phantom robots (past n) fall in the
+          // dead part of the position buffer (it holds 3 x 16R x 16 words), and lanes of the
+          // columns past m (zero products) write distinct spare words after the 3 x 16R rows of m.
           float* gp = wbuf;
+          const bool cv = col < m;
+          const int spare = NR * 3 * m + (col - m) + (16 - m) * grp;
 #pragma unroll
           for (int rr = 0; rr < R; ++rr)
 #pragma unroll
@@ -817,7 +837,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const int robot = 16 * rr + 4 * grp + r;
-                if (robot < n && col < m) gp[(robot * 3 + d) * m + col] = gacc[rr][d][r];
+                gp[cv ? (robot * 3 + d) * m + col : spare] = gacc[rr][d][r];
               }
           if (grp == 0) {
 #pragma unroll
@@ -840,7 +860,148 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         // Every load of the step is issued first, from clamped (always valid) addresses, and a
         // scheduling barrier keeps the arithmetic after them, so the step waits for LDS once; y is
         // zero past the free coefficients, so the QP product needs no guard either.
-        if (wave < TAILW) {
+        if constexpr (QUART) {
+          // Multiplier step and QP step of row (robot, ax), ax = this wave: lane robot + 16 q takes
+          // the free coefficients f = q, q + 4, ... and the pinned ones r = q, q + 4.  Every lane
+          // gathers its row's y and mean(y) from the four quarters with row swaps.
+          const float* gp0 = smem + L.tiles;
+          const int q4 = lane >> 4, rb = lane & 15, ax = wave;
+          const bool on = rb < n;
+          const int row = (on ? rb : 0) * 3 + ax;
+          int qf[FQ], qpn[2];
+          float xv[FQ], lf[FQ], xb[FQ], cr[FQ], gf[FQ][W], lp[2], gn[2][W];
+#pragma unroll
+          for (int j = 0; j < FQ; ++j) {
+            const int f = q4 + 4 * j, fc = f < mf ? f : 0;
+            qf[j] = row * m + 3 + fc;
+            xv[j] = sxi[qf[j]];
+            lf[j] = slam[qf[j]];
+            xb[j] = sxb[qf[j]];
+            cr[j] = scorr[row * (mf > 0 ? mf : 1) + fc];
+#pragma unroll
+            for (int ww = 0; ww < W; ++ww) gf[j][ww] = gp0[ww * L.per_wave + qf[j]];
+          }
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const int r = q4 + 4 * j, rc = r < kNFix ? r : 0;
+            qpn[j] = row * m + fixed_k(rc);
+            lp[j] = slam[qpn[j]];
+#pragma unroll
+            for (int ww = 0; ww < W; ++ww) gn[j][ww] = gp0[ww * L.per_wave + qpn[j]];
+          }
+          float cmax = s_cmx[row];   // running bound on |coefficient| of the row (pinned values included)
+          __builtin_amdgcn_sched_barrier(0);
+          auto sumw = [&](const float (&g)[W]) {
+            float s = g[0];
+#pragma unroll
+            for (int ww = 1; ww < W; ++ww) s += g[ww];
+            return s;
+          };
+          // the value of `v` in the four quarters of this lane's row, in quarter order
+          auto quarters = [&](float v, float* out) {
+            const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+            const auto b0 = __builtin_amdgcn_permlane32_swap(a[0], a[0], false, false);
+            const auto b1 = __builtin_amdgcn_permlane32_swap(a[1], a[1], false, false);
+            out[0] = __uint_as_float(b0[0]);
+            out[1] = __uint_as_float(b1[0]);
+            out[2] = __uint_as_float(b0[1]);
+            out[3] = __uint_as_float(b1[1]);
+          };
+          float ln[FQ], yo[FQ], gq[FQ];
+#pragma unroll
+          for (int j = 0; j < FQ; ++j) {
+            gq[j] = sumw(gf[j]);
+            ln[j] = lf[j] - gq[j];
+            float yv = xb[j] - xv[j] + ln[j] - gq[j];
+            if (k == 0) yv += cr[j];
+            yo[j] = (on && q4 + 4 * j < mf) ? yv : 0.0f;
+          }
+          // all free coefficients' y and mean(y): index f = q + 4 j (zero past mf)
+          float ya[4 * FQ], yba[4 * FQ];
+#pragma unroll
+          for (int j = 0; j < FQ; ++j) {
+            quarters(yo[j], ya + 4 * j);
+            quarters(group_sum<16>(yo[j]) * inv_n, yba + 4 * j);
+          }
+          float acc[FQ];
+#pragma unroll
+          for (int j = 0; j < FQ; ++j) {
+            const int f = q4 + 4 * j, fr = f < mf ? f : 0;
+            float a = 0.0f;
+#pragma unroll
+            for (int cc = 0; cc < QC; ++cc) {
+              const f4 x1 = *reinterpret_cast<const f4*>(sX1 + fr * (4 * QC) + 4 * cc);
+              const f4 x01 = *reinterpret_cast<const f4*>(sX1 + (mf + fr) * (4 * QC) + 4 * cc);
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                if (4 * cc + e < MFX) {
+                  a = fmaf(x1[e], ya[4 * cc + e], a);
+                  a = fmaf(x01[e], yba[4 * cc + e], a);
+                }
+            }
+            acc[j] = a;
+          }
+          float dmax = 0.0f;
+#pragma unroll
+          for (int j = 0; j < FQ; ++j)
+            if (q4 + 4 * j < mf) {
+              dmax = fmaxf(dmax, fabsf(acc[j]));
+              cmax = fmaxf(cmax, fabsf(xv[j] + acc[j]));
+            }
+          {
+            float t[4];
+            quarters(dmax, t);
+            dmax = fmaxf(fmaxf(t[0], t[1]), fmaxf(t[2], t[3]));
+            quarters(cmax, t);
+            cmax = fmaxf(fmaxf(t[0], t[1]), fmaxf(t[2], t[3]));
+          }
+          if (fpr && on) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              if (q4 + 4 * j < kNFix) {
+                const float g = sumw(gn[j]);
+                fpsum = fmaf(g, g, fpsum);
+                if (k == 0) {   // the pinned coefficients move to their boundary values in step 0
+                  const float dx = pinned(row, q4 + 4 * j) - sxi[qpn[j]];
+                  fpsum = fmaf(dx, dx, fpsum);
+                }
+              }
+#pragma unroll
+            for (int j = 0; j < FQ; ++j)
+              if (q4 + 4 * j < mf) {
+                fpsum = fmaf(gq[j], gq[j], fpsum);
+                fpsum = fmaf(acc[j], acc[j], fpsum);
+              }
+          }
+          if (on) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              const int r = q4 + 4 * j;
+              if (r < kNFix) {
+                slam[qpn[j]] = lp[j] - sumw(gn[j]);
+                if (k == 0) {
+                  const float xp = pinned(row, r);
+                  sxi[qpn[j]] = xp;
+                  if constexpr (MP != 0) put_split(rb, ax, fixed_k(r), xp);
+                }
+              }
+            }
+#pragma unroll
+            for (int j = 0; j < FQ; ++j) {
+              const int f = q4 + 4 * j;
+              if (f < mf) {
+                const float xn = xv[j] + acc[j];
+                slam[qf[j]] = ln[j];
+                sxi[qf[j]] = xn;
+                if constexpr (MP != 0) put_split(rb, ax, 3 + f, xn);
+              }
+            }
+            if (q4 == 0) {
+              s_dxi[row] = dmax;
+              s_cmx[row] = cmax;   // (the other quarters read it above, in the same wave)
+            }
+          }
+        } else if (wave < TAILW) {
           const float* gp0 = smem + L.tiles;
           const int hl = HALVES == 2 ? (lane >> 5) : 0;
           const int trow = wave * (64 / HALVES) + (HALVES == 2 ? (lane & 31) : lane);
