@@ -380,6 +380,18 @@ def run_single(args, wl):
             "roofline_frac": roofline([(p.cfg, S)], K, ms2, args.compare, None)["frac"],
             "per_sample_rel_deviation_at_equal_iters": {"max": float(dev.max()), "median": float(dev.median())},
         }
+    if compare and prec == "bf16":
+        # the other 16-bit form (fp16 hi/lo operands carry 22 bits against bf16's 16) at its own
+        # equal-residual K, timed the same way
+        k16, crit16, _, _ = equal_residual_iters(sf, xb, bv, "fp16", K, (n2, p99b, vmaxb), K + args.equal_residual_slack)
+        if k16 is not None:
+            ms16, out16 = form("fp16", k16, args.steps, args.warmup)
+            n16, _, _ = judge(sf, out16.xi, bv, "fp16")
+            line["fp16_form"] = {"iters": k16, "ms_per_step": round(ms16, 4), "value": round(n16 / (ms16 / 1e3), 1),
+                                 "converged_fraction": round(n16 / S, 6),
+                                 "roofline_frac": roofline([(p.cfg, S)], k16, ms16, "fp16", None)["frac"]}
+        else:
+            line["fp16_form"] = {"iters": None, "criteria": crit16}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, min(args.cpu_samples, S), K)
     return line

@@ -446,71 +446,91 @@ void tune_store(const std::string& sig, int waves, int grid, double ms) {
 
 sf_status autotune(sf_handle h, const Plan* p, sf::FastPlan& fp, const sf::LaunchArgs& a, int precision) {
   const int pi = precision & 3;
-  if (fp.tuned_w[pi] > 0) return SF_OK;
-  const std::string sig = tune_signature(h, p, precision) + (fp.batched ? ":persistent" : ":single");
-  int cw = 0, cg = 0;
-  if (tune_lookup(sig, &cw, &cg)) {
-    fp.tuned_w[pi] = cw;
-    fp.tuned_grid[pi] = cg;
+  if (fp.batched ? fp.tuned_wc[pi][0] > 0 : fp.tuned_w[pi] > 0) return SF_OK;
+  // a single-shape plan is tuned as a whole; a persistent plan per robot-tile class (each class is its
+  // own kernel with its own register budget, so each gets its own waves per workgroup and grid)
+  const std::string base = tune_signature(h, p, precision) + (fp.batched ? ":persistent" : ":single");
+  const int nsub = fp.batched ? fp.n_cls : 1;
+  auto sig_of = [&](int sub) { return fp.batched ? base + ":c" + std::to_string(sub) : base; };
+  int cw[2] = {0, 0}, cg[2] = {0, 0};
+  bool cached = true;
+  for (int sub = 0; sub < nsub; ++sub) cached = cached && tune_lookup(sig_of(sub), &cw[sub], &cg[sub]);
+  if (cached) {
+    if (fp.batched)
+      for (int sub = 0; sub < nsub; ++sub) {
+        fp.tuned_wc[pi][sub] = cw[sub];
+        fp.tuned_gc[pi][sub] = cg[sub];
+      }
+    else
+      fp.tuned_w[pi] = cw[0];
     return SF_OK;
   }
-  // candidates: waves per workgroup x (persistent only) workgroups in flight
-  std::vector<std::pair<int, int>> cand;
-  for (int W : {2, 3, 4}) {
-    if (fp.ws && W > 3) continue;   // the workspace instances have 2 or 3 waves per workgroup
-    if (!fp.batched) {
-      cand.push_back({W, 0});
-      continue;
-    }
-    std::vector<int> grids;
-    for (int k = 1; k <= 6; ++k) grids.push_back(std::min(fp.ncu * k, p->n_items));
-    std::sort(grids.begin(), grids.end());
-    grids.erase(std::unique(grids.begin(), grids.end()), grids.end());
-    for (int g : grids) cand.push_back({W, g});
-  }
   // trial launches: single-shape plans are cheap, so they get longer trials, two warm-ups (the first
-  // launches of a kernel also grow its scratch backing) and the best of three; persistent plans
-  // over large ragged batches the best of two 30-iteration runs
+  // launches of a kernel also grow its scratch backing) and the best of three; persistent classes over
+  // large ragged batches the best of two 30-iteration runs
   sf::LaunchArgs t = a;
   t.iters = std::max(1, std::min(a.iters, fp.batched ? 30 : 50));
   t.status_out = nullptr;   // trial launches read and write no status
   const int warm = fp.batched ? 1 : 2, reps = fp.batched ? 2 : 3;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(SF_EDEVICE, "events");
-  auto run = [&](const std::pair<int, int>& c) {
-    return fp.batched ? sf::fast_launch_batched(fp, t, h->d_tab32, h->d_a16, precision, c.second, c.first)
-                      : sf::fast_launch_single(fp, t, h->d_tab32, h->d_a16, precision, c.first);
-  };
-  std::pair<int, int> best = cand[0];
-  float best_ms = 1e30f;
-  for (const auto& c : cand) {
-    hipError_t e = hipSuccess;
-    for (int i = 0; i < warm && e == hipSuccess; ++i) e = run(c);
-    float ms = 1e30f;
-    for (int rep = 0; rep < reps && e == hipSuccess; ++rep) {
-      e = hipEventRecord(e0, a.stream);
-      if (e == hipSuccess) e = run(c);
-      if (e == hipSuccess) e = hipEventRecord(e1, a.stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float one = 0.0f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&one, e0, e1);
-      ms = std::min(ms, one);
+  for (int sub = 0; sub < nsub; ++sub) {
+    // candidates: waves per workgroup x (persistent only) workgroups in flight
+    std::vector<std::pair<int, int>> cand;
+    for (int W : {2, 3, 4}) {
+      if (fp.ws && W > 3) continue;   // the workspace instances have 2 or 3 waves per workgroup
+      if (!fp.batched) {
+        cand.push_back({W, 0});
+        continue;
+      }
+      std::vector<int> grids;
+      for (int k = 1; k <= 6; ++k) grids.push_back(std::min(fp.ncu * k, fp.cls[sub].n_items));
+      std::sort(grids.begin(), grids.end());
+      grids.erase(std::unique(grids.begin(), grids.end()), grids.end());
+      for (int g : grids) cand.push_back({W, g});
     }
-    if (e != hipSuccess) {
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      return hip_fail(e, "autotune");
+    auto run = [&](const std::pair<int, int>& c) {
+      if (!fp.batched) return sf::fast_launch_single(fp, t, h->d_tab32, h->d_a16, precision, c.first);
+      int W2[2] = {2, 2}, G2[2] = {0, 0};
+      W2[sub] = c.first;
+      G2[sub] = c.second;
+      return sf::fast_launch_batched(fp, t, h->d_tab32, h->d_a16, precision, G2, W2, 1 << sub);
+    };
+    std::pair<int, int> best = cand[0];
+    float best_ms = 1e30f;
+    for (const auto& c : cand) {
+      hipError_t e = hipSuccess;
+      for (int i = 0; i < warm && e == hipSuccess; ++i) e = run(c);
+      float ms = 1e30f;
+      for (int rep = 0; rep < reps && e == hipSuccess; ++rep) {
+        e = hipEventRecord(e0, a.stream);
+        if (e == hipSuccess) e = run(c);
+        if (e == hipSuccess) e = hipEventRecord(e1, a.stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float one = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&one, e0, e1);
+        ms = std::min(ms, one);
+      }
+      if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return hip_fail(e, "autotune");
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
     }
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = c;
+    if (fp.batched) {
+      fp.tuned_wc[pi][sub] = best.first;
+      fp.tuned_gc[pi][sub] = best.second;
+    } else {
+      fp.tuned_w[pi] = best.first;
     }
+    tune_store(sig_of(sub), best.first, best.second, best_ms);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  fp.tuned_w[pi] = best.first;
-  fp.tuned_grid[pi] = best.second;
-  tune_store(sig, best.first, best.second, best_ms);
   return SF_OK;
 }
 
@@ -846,8 +866,11 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
   hipError_t e;
   if (flags & SF_USE_GRAPH) {
     std::vector<uintptr_t> key = {(uintptr_t)precision, (uintptr_t)flags, (uintptr_t)iters, (uintptr_t)a.ckpt_every,
-                                  (uintptr_t)fp, (uintptr_t)(fp ? fp->tuned_grid[precision & 3] : 0),
-                                  (uintptr_t)(fp ? fp->tuned_w[precision & 3] : 0),
+                                  (uintptr_t)fp, (uintptr_t)(fp ? fp->tuned_w[precision & 3] : 0),
+                                  (uintptr_t)(fp ? fp->tuned_wc[precision & 3][0] : 0),
+                                  (uintptr_t)(fp ? fp->tuned_wc[precision & 3][1] : 0),
+                                  (uintptr_t)(fp ? fp->tuned_gc[precision & 3][0] : 0),
+                                  (uintptr_t)(fp ? fp->tuned_gc[precision & 3][1] : 0),
                                   (uintptr_t)xi_bar, (uintptr_t)bvals, (uintptr_t)xi0, (uintptr_t)lam0,
                                   (uintptr_t)xi_out, (uintptr_t)lam_out, (uintptr_t)resid_out,
                                   (uintptr_t)status_out, (uintptr_t)ckpt};

@@ -32,8 +32,9 @@ struct FastPlan {
   FastClass cls[2];                     // 17-32 robots, then up to 16 (empty classes left out)
   int n_cls = 0;
   int ncu = 0;
-  int tuned_grid[4] = {0, 0, 0, 0};     // autotuned persistent workgroups per precision (0 = not tuned)
   int tuned_w[4] = {0, 0, 0, 0};        // autotuned waves per workgroup per precision (0 = not tuned)
+  int tuned_wc[4][2] = {};              // persistent launches: autotuned waves per workgroup per precision
+  int tuned_gc[4][2] = {};              // and class, and workgroups (0 = not tuned / the class default)
   bool ws = false;                      // some config has a workspace: kernels with its rows, and
                                         // 2 or 3 waves per workgroup
 };
@@ -42,8 +43,10 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
                           const std::vector<WorkItem>& items, bool persistent, FastPlan& out);
 void fast_plan_free(FastPlan& p);
 hipError_t fast_launch(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16, int precision);
+// Persistent launch sequence: the classes in cls_mask (bit c = class c), with per-class waves per
+// workgroup W[c] and workgroup counts grid[c] (0 = the class's default).
 hipError_t fast_launch_batched(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16,
-                               int precision, int grid, int W);
+                               int precision, const int* grid, const int* W, int cls_mask);
 hipError_t fast_launch_single(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16,
                               int precision, int W);
 

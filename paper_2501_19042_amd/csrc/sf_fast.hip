@@ -11,17 +11,23 @@ std::string fast_last_error() { return g_fast_err; }
 void fast_set_error(const char* msg) { g_fast_err = msg; }
 
 hipError_t fast_launch_single_p0_w0(const FastPlan&, const LaunchArgs&, const float*, const uint4*, int);
-hipError_t fast_launch_batched_p0_w0(const FastPlan&, const LaunchArgs&, const float*, const uint4*, int, int);
+hipError_t fast_launch_batched_p0_w0(const FastPlan&, const LaunchArgs&, const float*, const uint4*, const int*, const int*,
+                                     int);
 hipError_t fast_launch_single_p0_w1(const FastPlan&, const LaunchArgs&, const float*, const uint4*, int);
-hipError_t fast_launch_batched_p0_w1(const FastPlan&, const LaunchArgs&, const float*, const uint4*, int, int);
+hipError_t fast_launch_batched_p0_w1(const FastPlan&, const LaunchArgs&, const float*, const uint4*, const int*, const int*,
+                                     int);
 hipError_t fast_launch_single_p1_w0(const FastPlan&, const LaunchArgs&, const float*, const uint4*, int);
-hipError_t fast_launch_batched_p1_w0(const FastPlan&, const LaunchArgs&, const float*, const uint4*, int, int);
+hipError_t fast_launch_batched_p1_w0(const FastPlan&, const LaunchArgs&, const float*, const uint4*, const int*, const int*,
+                                     int);
 hipError_t fast_launch_single_p1_w1(const FastPlan&, const LaunchArgs&, const float*, const uint4*, int);
-hipError_t fast_launch_batched_p1_w1(const FastPlan&, const LaunchArgs&, const float*, const uint4*, int, int);
+hipError_t fast_launch_batched_p1_w1(const FastPlan&, const LaunchArgs&, const float*, const uint4*, const int*, const int*,
+                                     int);
 hipError_t fast_launch_single_p2_w0(const FastPlan&, const LaunchArgs&, const float*, const uint4*, int);
-hipError_t fast_launch_batched_p2_w0(const FastPlan&, const LaunchArgs&, const float*, const uint4*, int, int);
+hipError_t fast_launch_batched_p2_w0(const FastPlan&, const LaunchArgs&, const float*, const uint4*, const int*, const int*,
+                                     int);
 hipError_t fast_launch_single_p2_w1(const FastPlan&, const LaunchArgs&, const float*, const uint4*, int);
-hipError_t fast_launch_batched_p2_w1(const FastPlan&, const LaunchArgs&, const float*, const uint4*, int, int);
+hipError_t fast_launch_batched_p2_w1(const FastPlan&, const LaunchArgs&, const float*, const uint4*, const int*, const int*,
+                                     int);
 
 using fastk::fast_lds_plan;
 using fastk::waves_per_simd;
@@ -215,13 +221,19 @@ void fast_plan_free(FastPlan& p) {
 }
 
 hipError_t fast_launch_batched(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16,
-                               int precision, int grid, int W) {
+                               int precision, const int* grid, const int* W, int cls_mask) {
   const uint4* t = static_cast<const uint4*>(a16);
   const bool ws = p.ws;
   switch (precision) {
-    case SF_FP32: return ws ? fast_launch_batched_p0_w1(p, a, tab32, t, grid, W) : fast_launch_batched_p0_w0(p, a, tab32, t, grid, W);
-    case SF_BF16: return ws ? fast_launch_batched_p1_w1(p, a, tab32, t, grid, W) : fast_launch_batched_p1_w0(p, a, tab32, t, grid, W);
-    case SF_FP16: return ws ? fast_launch_batched_p2_w1(p, a, tab32, t, grid, W) : fast_launch_batched_p2_w0(p, a, tab32, t, grid, W);
+    case SF_FP32:
+      return ws ? fast_launch_batched_p0_w1(p, a, tab32, t, grid, W, cls_mask)
+                : fast_launch_batched_p0_w0(p, a, tab32, t, grid, W, cls_mask);
+    case SF_BF16:
+      return ws ? fast_launch_batched_p1_w1(p, a, tab32, t, grid, W, cls_mask)
+                : fast_launch_batched_p1_w0(p, a, tab32, t, grid, W, cls_mask);
+    case SF_FP16:
+      return ws ? fast_launch_batched_p2_w1(p, a, tab32, t, grid, W, cls_mask)
+                : fast_launch_batched_p2_w0(p, a, tab32, t, grid, W, cls_mask);
     default:
       g_fast_err = "precision not implemented in the MFMA kernels";
       return hipErrorNotSupported;
@@ -229,13 +241,17 @@ hipError_t fast_launch_batched(const FastPlan& p, const LaunchArgs& a, const flo
 }
 
 hipError_t fast_launch(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16, int precision) {
-  int W = p.tuned_w[precision & 3] > 0 ? p.tuned_w[precision & 3] : p.Wp[precision & 3];
-  if (p.ws && W > 3) W = 3;   // the workspace instances have 2 or 3 waves per workgroup
+  const int pi = precision & 3;
+  auto waves = [&](int tuned) {
+    int W = tuned > 0 ? tuned : p.Wp[pi];
+    if (p.ws && W > 3) W = 3;   // the workspace instances have 2 or 3 waves per workgroup
+    return W;
+  };
   if (p.batched) {
-    const int g = p.tuned_grid[precision & 3];
-    return fast_launch_batched(p, a, tab32, a16, precision, g, W);
+    const int W[2] = {waves(p.tuned_wc[pi][0]), waves(p.tuned_wc[pi][1])};
+    return fast_launch_batched(p, a, tab32, a16, precision, p.tuned_gc[pi], W, 3);
   }
-  return fast_launch_single(p, a, tab32, a16, precision, W);
+  return fast_launch_single(p, a, tab32, a16, precision, waves(p.tuned_w[pi]));
 }
 
 hipError_t fast_launch_single(const FastPlan& p, const LaunchArgs& a, const float* tab32, const void* a16,

@@ -1409,21 +1409,20 @@ hipError_t launch_class(const FastClass& C, const FastArgs& f, int grid, int* qu
   return hipGetLastError();
 }
 
-// grid > 0: workgroups per class launch (at most its work items); 0: each class's default.
-template <int KS, int W, int MP, int WS>
-hipError_t launch_batched(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16, int grid) {
-  hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, a.stream, p.d_queue, p.n_cls);
-  for (int ci = 0; ci < p.n_cls; ++ci) {
-    const FastClass& C = p.cls[ci];
-    FastArgs f = make_fast_args(a, tab32, a16);
-    f.items = p.d_items_sorted + C.offset;
-    f.n_items = C.n_items;
-    const int g = std::max(1, std::min(C.n_items, grid > 0 ? grid : C.grid));
-    const hipError_t e = C.R == 1 ? launch_class<1, KS, W, MP, WS>(C, f, g, p.d_queue + ci, a.stream)
-                                  : launch_class<2, KS, W, MP, WS>(C, f, g, p.d_queue + ci, a.stream);
-    if (e != hipSuccess) return e;
+// One class of a persistent launch sequence with W waves per workgroup; grid > 0: workgroups (at most
+// the class's work items), 0: the class's default.
+template <int R, int KS, int MP, int WS>
+hipError_t launch_class_w(const FastClass& C, const FastArgs& f, int grid, int W, int* queue, hipStream_t stream) {
+  switch (W) {
+    case 2: return launch_class<R, KS, 2, MP, WS>(C, f, grid, queue, stream);
+    case 3: return launch_class<R, KS, 3, MP, WS>(C, f, grid, queue, stream);
+    case 4:
+      if constexpr (WS == 0) return launch_class<R, KS, 4, MP, WS>(C, f, grid, queue, stream);
+      break;
+    default: break;
   }
-  return hipSuccess;
+  fast_set_error("no persistent kernel instance for this shape");
+  return hipErrorNotSupported;
 }
 
 // Single-shape launch of the instance for (R, KS, W) of this precision and workspace flag.
@@ -1469,37 +1468,36 @@ hipError_t launch_single_mp(const FastPlan& p, const LaunchArgs& a, const float*
   return hipErrorNotSupported;
 }
 
-// Persistent launch sequence (one kernel per robot-tile class) of this precision and workspace flag.
+// Persistent launch sequence (one kernel per robot-tile class) of this precision and workspace flag:
+// the queue heads are reset, then each class selected by cls_mask runs with its own waves per
+// workgroup W[c] and workgroup count grid[c] (0 = the class's default).
 template <int MP, int WS>
-hipError_t launch_batched_mp(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16, int grid,
-                             int W) {
-  const int key = p.KS * 10 + W;
-  if constexpr (WS == 0) {
-    switch (key) {
-      case 22: return launch_batched<2, 2, MP, 0>(p, a, tab32, a16, grid);
-      case 23: return launch_batched<2, 3, MP, 0>(p, a, tab32, a16, grid);
-      case 24: return launch_batched<2, 4, MP, 0>(p, a, tab32, a16, grid);
-      case 32: return launch_batched<3, 2, MP, 0>(p, a, tab32, a16, grid);
-      case 33: return launch_batched<3, 3, MP, 0>(p, a, tab32, a16, grid);
-      case 34: return launch_batched<3, 4, MP, 0>(p, a, tab32, a16, grid);
-      case 42: return launch_batched<4, 2, MP, 0>(p, a, tab32, a16, grid);
-      case 43: return launch_batched<4, 3, MP, 0>(p, a, tab32, a16, grid);
-      case 44: return launch_batched<4, 4, MP, 0>(p, a, tab32, a16, grid);
-      default: break;
+hipError_t launch_batched_mp(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16,
+                             const int* grid, const int* W, int cls_mask) {
+  hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, a.stream, p.d_queue, p.n_cls);
+  for (int ci = 0; ci < p.n_cls; ++ci) {
+    if (!(cls_mask & (1 << ci))) continue;
+    const FastClass& C = p.cls[ci];
+    FastArgs f = make_fast_args(a, tab32, a16);
+    f.items = p.d_items_sorted + C.offset;
+    f.n_items = C.n_items;
+    const int g = std::max(1, std::min(C.n_items, grid[ci] > 0 ? grid[ci] : C.grid));
+    int* q = p.d_queue + ci;
+    hipError_t e;
+    switch (C.R * 10 + p.KS) {
+      case 12: e = launch_class_w<1, 2, MP, WS>(C, f, g, W[ci], q, a.stream); break;
+      case 13: e = launch_class_w<1, 3, MP, WS>(C, f, g, W[ci], q, a.stream); break;
+      case 14: e = launch_class_w<1, 4, MP, WS>(C, f, g, W[ci], q, a.stream); break;
+      case 22: e = launch_class_w<2, 2, MP, WS>(C, f, g, W[ci], q, a.stream); break;
+      case 23: e = launch_class_w<2, 3, MP, WS>(C, f, g, W[ci], q, a.stream); break;
+      case 24: e = launch_class_w<2, 4, MP, WS>(C, f, g, W[ci], q, a.stream); break;
+      default:
+        fast_set_error("no persistent kernel instance for this shape");
+        return hipErrorNotSupported;
     }
-  } else {
-    switch (key) {
-      case 22: return launch_batched<2, 2, MP, 1>(p, a, tab32, a16, grid);
-      case 23: return launch_batched<2, 3, MP, 1>(p, a, tab32, a16, grid);
-      case 32: return launch_batched<3, 2, MP, 1>(p, a, tab32, a16, grid);
-      case 33: return launch_batched<3, 3, MP, 1>(p, a, tab32, a16, grid);
-      case 42: return launch_batched<4, 2, MP, 1>(p, a, tab32, a16, grid);
-      case 43: return launch_batched<4, 3, MP, 1>(p, a, tab32, a16, grid);
-      default: break;
-    }
+    if (e != hipSuccess) return e;
   }
-  fast_set_error("no persistent kernel instance for this shape");
-  return hipErrorNotSupported;
+  return hipSuccess;
 }
 
 }  // namespace

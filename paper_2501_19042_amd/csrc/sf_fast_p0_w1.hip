@@ -9,8 +9,8 @@ hipError_t fast_launch_single_p0_w1(const FastPlan& p, const LaunchArgs& a, cons
 }
 
 hipError_t fast_launch_batched_p0_w1(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16,
-                                      int grid, int W) {
-  return fastk::launch_batched_mp<0, 1>(p, a, tab32, a16, grid, W);
+                                      const int* grid, const int* W, int cls_mask) {
+  return fastk::launch_batched_mp<0, 1>(p, a, tab32, a16, grid, W, cls_mask);
 }
 
 }  // namespace sf

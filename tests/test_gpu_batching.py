@@ -162,3 +162,36 @@ def test_every_launch_shape_matches_oracle(P, tmp_path, monkeypatch, prec, n):
         e = ((g - rx.reshape(6, -1)).abs().amax(1) / rx.reshape(6, -1).abs().amax(1)).numpy()
         print(f"n={n} {prec} W={w}: max rel err {e.max():.2e}", flush=True)
         assert e.max() <= bound, (w, e)
+
+
+@pytest.mark.parametrize("shapes", [((2, 0), (3, 0)), ((4, 256), (2, 300))])
+def test_persistent_classes_take_their_own_launch_shapes(P, tmp_path, monkeypatch, shapes):
+    """Each robot-tile class of a persistent launch (17-32 robots, then up to 16) runs with its own
+    waves per workgroup and workgroup count, pinned through the autotuner's cache (one entry per
+    class); the results stay within the FP32 tolerance of the oracle and nothing is re-tuned."""
+    probs = ragged_problems()
+    sf = P.SafetyFilter([p.cfg for p in probs])
+    batch = P.Batch([(i, p.xi_bar.shape[0]) for i, p in enumerate(probs)])
+    xb, bv = pack(probs)
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("SWARMSF_TUNE_CACHE", str(cache))
+    sf.project(xb, bv, 10, batch=batch, precision="fp32", autotune=True)
+    torch.cuda.synchronize()
+    keys = sorted({l.split('"key": "')[1].split('"')[0] for l in cache.read_text().splitlines()})
+    assert len(keys) == 2 and keys[0].endswith(":c0") and keys[1].endswith(":c1"), keys
+    cache.write_text("".join('{"key": "%s", "waves": %d, "grid": %d, "ms": 1.0}\n' % (k, w, g)
+                             for k, (w, g) in zip(keys, shapes)))
+    iters = 40
+    out = P.SafetyFilter([p.cfg for p in probs]).project(xb, bv, iters, batch=batch, precision="fp32",
+                                                         autotune=True)
+    torch.cuda.synchronize()
+    assert len(cache.read_text().splitlines()) == 2
+    o = 0
+    for p in probs:
+        s = O.build_system(p.cfg)
+        rx, _, _ = O.sf_project(s, torch.tensor(p.xi_bar), torch.tensor(p.bvals), iters)
+        S = p.xi_bar.shape[0]
+        g = out.xi[o:o + p.xi_bar.size].reshape(rx.shape).cpu().double()
+        e = ((g - rx).abs().reshape(S, -1).amax(1) / rx.abs().reshape(S, -1).amax(1)).numpy()
+        assert e.max() <= 1e-4, (p.cfg.n_robots, e)
+        o += p.xi_bar.size
