@@ -50,14 +50,14 @@ template <typename T>
 __device__ __forceinline__ void coll_jt(const T* r, const T* v, int D, T ia2, T ib2, T* out) {
   T ss = r[0] * r[0] * ia2 + r[1] * r[1] * ia2;
   if (D == 3) ss += r[2] * r[2] * ib2;
-  for (int d = 0; d < D; ++d) out[d] = T(0);
+  SF_FOR_DIM(d, D) out[d] = T(0);
   if (ss >= tiny_sq<T>() && ss < T(1)) {
     const T rs = rsq<T>(ss);
     const T f = T(1) - rs;
     T rv = T(0);
-    for (int d = 0; d < D; ++d) rv += r[d] * v[d];
+    SF_FOR_DIM(d, D) rv += r[d] * v[d];
     const T k3 = rs * rs * rs * rv;
-    for (int d = 0; d < D; ++d) out[d] = f * v[d] + k3 * r[d] * (d == 2 ? ib2 : ia2);
+    SF_FOR_DIM(d, D) out[d] = f * v[d] + k3 * r[d] * (d == 2 ? ib2 : ia2);
   }
 }
 
@@ -66,14 +66,14 @@ template <typename T>
 __device__ __forceinline__ void ball_jt(const T* v, const T* w, int D, T lim, T* out) {
   T ss = v[0] * v[0] + v[1] * v[1];
   if (D == 3) ss += v[2] * v[2];
-  for (int d = 0; d < D; ++d) out[d] = T(0);
+  SF_FOR_DIM(d, D) out[d] = T(0);
   if (ss > lim * lim) {
     const T rs = rsq<T>(ss);
     const T h = T(1) - lim * rs;
     T vw = T(0);
-    for (int d = 0; d < D; ++d) vw += v[d] * w[d];
+    SF_FOR_DIM(d, D) vw += v[d] * w[d];
     const T k3 = lim * rs * rs * rs * vw;
-    for (int d = 0; d < D; ++d) out[d] = h * w[d] + k3 * v[d];
+    SF_FOR_DIM(d, D) out[d] = h * w[d] + k3 * v[d];
   }
 }
 
@@ -83,18 +83,18 @@ template <typename T>
 __device__ __forceinline__ void ws_jt(const T* p, const T* w, int D, const T* wc, T ia2, T ib2, T* out) {
   T q[3] = {T(0), T(0), T(0)};
   T ss = T(0);
-  for (int d = 0; d < D; ++d) {
+  SF_FOR_DIM(d, D) {
     q[d] = p[d] - wc[d];
     ss += q[d] * q[d] * (d == 2 ? ib2 : ia2);
   }
-  for (int d = 0; d < D; ++d) out[d] = T(0);
+  SF_FOR_DIM(d, D) out[d] = T(0);
   if (ss > T(1)) {
     const T rs = rsq<T>(ss);
     const T f = T(1) - rs;
     T qw = T(0);
-    for (int d = 0; d < D; ++d) qw += q[d] * w[d];
+    SF_FOR_DIM(d, D) qw += q[d] * w[d];
     const T k3 = rs * rs * rs * qw;
-    for (int d = 0; d < D; ++d) out[d] = f * w[d] + k3 * q[d] * (d == 2 ? ib2 : ia2);
+    SF_FOR_DIM(d, D) out[d] = f * w[d] + k3 * q[d] * (d == 2 ? ib2 : ia2);
   }
 }
 
@@ -134,30 +134,30 @@ __device__ void resid_term(const Ctx<T>& x, const Lds<T>& L, T* Wt, T* GY, T* gx
       for (int j = 0; j < n; ++j) {
         if (j == i) continue;
         T rp[3], rn[3], R[3], gr[3], jt[3];
-        for (int d = 0; d < D; ++d) {
+        SF_FOR_DIM(d, D) {
           rp[d] = L.Y[(i * D + d) * TT + tt] - L.Y[(j * D + d) * TT + tt];
           rn[d] = Wt[(i * D + d) * TT + tt] - Wt[(j * D + d) * TT + tt];
         }
         coll_resid<T>(rp, D, x.ia2, x.ib2, x.a, x.b, i < j, R);
-        for (int d = 0; d < D; ++d) gr[d] = T(2) * gres * (rn[d] - (rp[d] - R[d]));
+        SF_FOR_DIM(d, D) gr[d] = T(2) * gres * (rn[d] - (rp[d] - R[d]));
         coll_jt<T>(rp, gr, D, x.ia2, x.ib2, jt);
-        for (int d = 0; d < D; ++d) {
+        SF_FOR_DIM(d, D) {
           Ai[d] += gr[d];
           Bi[d] += jt[d] - gr[d];
         }
       }
       if (c.ws_on) {   // workspace rows: r_p = p_new - e(p_prev)
         T v[3], R[3], gr[3], jt[3];
-        for (int d = 0; d < D; ++d) v[d] = L.Y[(i * D + d) * TT + tt];
+        SF_FOR_DIM(d, D) v[d] = L.Y[(i * D + d) * TT + tt];
         ws_resid<T>(v, D, x.wc, x.ws_ia2, x.ws_ib2, R);
-        for (int d = 0; d < D; ++d) gr[d] = T(2) * gres * (Wt[(i * D + d) * TT + tt] - (v[d] - R[d]));
+        SF_FOR_DIM(d, D) gr[d] = T(2) * gres * (Wt[(i * D + d) * TT + tt] - (v[d] - R[d]));
         ws_jt<T>(v, gr, D, x.wc, x.ws_ia2, x.ws_ib2, jt);
-        for (int d = 0; d < D; ++d) {
+        SF_FOR_DIM(d, D) {
           Ai[d] += gr[d];
           Bi[d] += jt[d] - gr[d];
         }
       }
-      for (int d = 0; d < D; ++d) {
+      SF_FOR_DIM(d, D) {
         GY[(i * D + d) * TT + tt] = Ai[d];
         L.Rb[(i * D + d) * TT + tt] = Bi[d];
       }
@@ -166,12 +166,12 @@ __device__ void resid_term(const Ctx<T>& x, const Lds<T>& L, T* Wt, T* GY, T* gx
         if (!on) continue;
         const T lim = bsel == 1 ? x.vmax : x.amax;
         T v[3], R[3], gr[3], jt[3];
-        for (int d = 0; d < D; ++d) v[d] = L.Y[((bsel * n + i) * D + d) * TT + tt];
+        SF_FOR_DIM(d, D) v[d] = L.Y[((bsel * n + i) * D + d) * TT + tt];
         ball_resid<T>(v, D, lim, R);
-        for (int d = 0; d < D; ++d)
+        SF_FOR_DIM(d, D)
           gr[d] = T(2) * gres * (Wt[((bsel * n + i) * D + d) * TT + tt] - (v[d] - R[d]));
         ball_jt<T>(v, gr, D, lim, jt);
-        for (int d = 0; d < D; ++d) {
+        SF_FOR_DIM(d, D) {
           GY[((bsel * n + i) * D + d) * TT + tt] = gr[d];
           L.Rb[((bsel * n + i) * D + d) * TT + tt] = jt[d] - gr[d];
         }
@@ -337,35 +337,35 @@ adjoint_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, const
               for (int j = 0; j < n; ++j) {
                 if (j == i) continue;
                 T r[3], gr[3], jt[3];
-                for (int d = 0; d < D; ++d) {
+                SF_FOR_DIM(d, D) {
                   r[d] = L.Y[(i * D + d) * TT + tt] - L.Y[(j * D + d) * TT + tt];
                   gr[d] = x.rho_c * (Wt[(i * D + d) * TT + tt] - Wt[(j * D + d) * TT + tt]);
                 }
                 coll_jt<T>(r, gr, D, x.ia2, x.ib2, jt);
-                for (int d = 0; d < D; ++d) acc[d] += jt[d];
+                SF_FOR_DIM(d, D) acc[d] += jt[d];
               }
               if (c.ws_on) {   // workspace rows (weight rho_w) share the position basis
                 T p[3], gr[3], jt[3];
-                for (int d = 0; d < D; ++d) {
+                SF_FOR_DIM(d, D) {
                   p[d] = L.Y[(i * D + d) * TT + tt];
                   gr[d] = x.rho_c * x.ws_scale * Wt[(i * D + d) * TT + tt];
                 }
                 ws_jt<T>(p, gr, D, x.wc, x.ws_ia2, x.ws_ib2, jt);
-                for (int d = 0; d < D; ++d) acc[d] += jt[d];
+                SF_FOR_DIM(d, D) acc[d] += jt[d];
               }
-              for (int d = 0; d < D; ++d) GY[(i * D + d) * TT + tt] = acc[d];
+              SF_FOR_DIM(d, D) GY[(i * D + d) * TT + tt] = acc[d];
               for (int bsel = 1; bsel < 3; ++bsel) {
                 const bool on = bsel == 1 ? c.vel_on : c.acc_on;
                 if (!on) continue;
                 const T lim = bsel == 1 ? x.vmax : x.amax;
                 const T rho = bsel == 1 ? x.rho_v : x.rho_a;
                 T v[3], gr[3], jt[3];
-                for (int d = 0; d < D; ++d) {
+                SF_FOR_DIM(d, D) {
                   v[d] = L.Y[((bsel * n + i) * D + d) * TT + tt];
                   gr[d] = rho * Wt[((bsel * n + i) * D + d) * TT + tt];
                 }
                 ball_jt<T>(v, gr, D, lim, jt);
-                for (int d = 0; d < D; ++d) GY[((bsel * n + i) * D + d) * TT + tt] = jt[d];
+                SF_FOR_DIM(d, D) GY[((bsel * n + i) * D + d) * TT + tt] = jt[d];
               }
             }
             __syncthreads();

@@ -168,14 +168,14 @@ feasibility_kernel(const DevCfg* __restrict__ cfgs, const double* __restrict__ t
           const int i = q / TTc, tt = q - i * TTc;
           for (int j = i + 1; j < n; ++j) {
             double s = 0.0;
-            for (int d = 0; d < D; ++d) {
+            SF_FOR_DIM(d, D) {
               const double r = Y[(i * D + d) * TT + tt] - Y[(j * D + d) * TT + tt];
               s += r * r * (d == 2 ? c.inv_b2 : c.inv_a2);
             }
             smin = fmin(smin, s);
           }
           double v2 = 0.0, a2 = 0.0;
-          for (int d = 0; d < D; ++d) {
+          SF_FOR_DIM(d, D) {
             const double v = Y[((n + i) * D + d) * TT + tt];
             const double ac = Y[((2 * n + i) * D + d) * TT + tt];
             v2 += v * v;
@@ -185,7 +185,7 @@ feasibility_kernel(const DevCfg* __restrict__ cfgs, const double* __restrict__ t
           amx = fmax(amx, a2);
           if (c.ws_on) {   // ||M_w^{-1} (p_i - p_w)||^2 of eq. workspace_con
             double w2 = 0.0;
-            for (int d = 0; d < D; ++d) {
+            SF_FOR_DIM(d, D) {
               const double r = Y[(i * D + d) * TT + tt] - c.ws_c[d];
               w2 += r * r * (d == 2 ? c.ws_ib2 : c.ws_ia2);
             }

@@ -7,6 +7,11 @@
 
 #include <cfloat>
 
+// Loop over the D <= 3 coordinates with a constant trip count: the per-coordinate arrays (r[3],
+// R[3], ...) then have constant indices after unrolling and stay in registers; a loop bounded by
+// the run-time D would place them in private scratch memory.
+#define SF_FOR_DIM(d, D) _Pragma("unroll") for (int d = 0; d < 3; ++d) if (d < (D))
+
 namespace sf {
 namespace gen {
 
@@ -72,9 +77,9 @@ __device__ __forceinline__ void coll_resid(const T* r, int D, T ia2, T ib2, T a,
   if (D == 3) ss += r[2] * r[2] * ib2;
   if (ss >= tiny_sq<T>()) {
     const T f = min(T(0), T(1) - rsq<T>(ss));
-    for (int d = 0; d < D; ++d) R[d] = f * r[d];
+    SF_FOR_DIM(d, D) R[d] = f * r[d];
   } else {
-    for (int d = 0; d < D; ++d) R[d] = T(0);
+    SF_FOR_DIM(d, D) R[d] = T(0);
     if (D == 3) R[2] = lower ? -b : b;
     else R[0] = lower ? -a : a;
   }
@@ -85,7 +90,7 @@ __device__ __forceinline__ void ball_resid(const T* v, int D, T lim, T* R) {
   T ss = v[0] * v[0] + v[1] * v[1];
   if (D == 3) ss += v[2] * v[2];
   const T f = (ss > lim * lim) ? T(1) - lim * rsq<T>(ss) : T(0);
-  for (int d = 0; d < D; ++d) R[d] = f * v[d];
+  SF_FOR_DIM(d, D) R[d] = f * v[d];
 }
 
 // Residual of the workspace projection (eq. workspace_polar, d in [0, 1]) of a robot position p:
@@ -95,12 +100,12 @@ template <typename T>
 __device__ __forceinline__ void ws_resid(const T* p, int D, const T* wc, T ia2, T ib2, T* R) {
   T q[3] = {T(0), T(0), T(0)};
   T ss = T(0);
-  for (int d = 0; d < D; ++d) {
+  SF_FOR_DIM(d, D) {
     q[d] = p[d] - wc[d];
     ss += q[d] * q[d] * (d == 2 ? ib2 : ia2);
   }
   const T f = (ss > T(1)) ? T(1) - rsq<T>(ss) : T(0);
-  for (int d = 0; d < D; ++d) R[d] = f * q[d];
+  SF_FOR_DIM(d, D) R[d] = f * q[d];
 }
 
 // dst[b][i][d][tt] = sum_k basis[b][t0+tt][k] * src[i][d][k] for the enabled bases.
@@ -158,9 +163,9 @@ __device__ void residual_pass(const DevCfg& c, const T* __restrict__ basis, cons
       const int i = q / TTc, tt = q - (q / TTc) * TTc;
       for (int j = i + 1; j < n; ++j) {
         T rprev[3], R[3], nrm = T(0);
-        for (int d = 0; d < D; ++d) rprev[d] = L.Y[(i * D + d) * TT + tt] - L.Y[(j * D + d) * TT + tt];
+        SF_FOR_DIM(d, D) rprev[d] = L.Y[(i * D + d) * TT + tt] - L.Y[(j * D + d) * TT + tt];
         coll_resid<T>(rprev, D, ia2, ib2, a, b, true, R);
-        for (int d = 0; d < D; ++d) {
+        SF_FOR_DIM(d, D) {
           const T rp = (L.Rb[(i * D + d) * TT + tt] - L.Rb[(j * D + d) * TT + tt]) - (rprev[d] - R[d]);
           nrm += rp * rp;
         }
@@ -171,9 +176,9 @@ __device__ void residual_pass(const DevCfg& c, const T* __restrict__ basis, cons
         if ((bsel == 1 && !c.vel_on) || (bsel == 2 && !c.acc_on)) continue;
         const T lim = T(bsel == 1 ? c.vmax : c.amax);
         T v[3], R[3], nrm = T(0);
-        for (int d = 0; d < D; ++d) v[d] = L.Y[((bsel * n + i) * D + d) * TT + tt];
+        SF_FOR_DIM(d, D) v[d] = L.Y[((bsel * n + i) * D + d) * TT + tt];
         ball_resid<T>(v, D, lim, R);
-        for (int d = 0; d < D; ++d) {
+        SF_FOR_DIM(d, D) {
           const T rp = L.Rb[((bsel * n + i) * D + d) * TT + tt] - (v[d] - R[d]);
           nrm += rp * rp;
         }
@@ -183,9 +188,9 @@ __device__ void residual_pass(const DevCfg& c, const T* __restrict__ basis, cons
       if (c.ws_on) {   // workspace rows: positions against the previous iterate's targets
         const T wc[3] = {T(c.ws_c[0]), T(c.ws_c[1]), T(c.ws_c[2])};
         T v[3], R[3], nrm = T(0);
-        for (int d = 0; d < D; ++d) v[d] = L.Y[(i * D + d) * TT + tt];
+        SF_FOR_DIM(d, D) v[d] = L.Y[(i * D + d) * TT + tt];
         ws_resid<T>(v, D, wc, T(c.ws_ia2), T(c.ws_ib2), R);
-        for (int d = 0; d < D; ++d) {
+        SF_FOR_DIM(d, D) {
           const T rp = L.Rb[(i * D + d) * TT + tt] - (v[d] - R[d]);
           nrm += rp * rp;
         }
@@ -288,31 +293,31 @@ __device__ void iteration(const Ctx<T>& x, const Lds<T>& L, int TT, int k) {
     for (int q = threadIdx.x; q < n * TTc; q += blockDim.x) {
       const int i = q / TTc, tt = q - (q / TTc) * TTc;
       T xi_[3] = {T(0), T(0), T(0)}, C[3] = {T(0), T(0), T(0)};
-      for (int d = 0; d < D; ++d) xi_[d] = L.Y[(i * D + d) * TT + tt];
+      SF_FOR_DIM(d, D) xi_[d] = L.Y[(i * D + d) * TT + tt];
       for (int j = 0; j < n; ++j) {
         if (j == i) continue;
         T r[3], R[3];
-        for (int d = 0; d < D; ++d) r[d] = xi_[d] - L.Y[(j * D + d) * TT + tt];
+        SF_FOR_DIM(d, D) r[d] = xi_[d] - L.Y[(j * D + d) * TT + tt];
         coll_resid<T>(r, D, x.ia2, x.ib2, x.a, x.b, i < j, R);
-        for (int d = 0; d < D; ++d) C[d] += R[d];
+        SF_FOR_DIM(d, D) C[d] += R[d];
       }
       if (c.ws_on) {   // workspace rows share the position basis; weight rho_w = rho_c ws_scale
         T R[3];
         ws_resid<T>(xi_, D, x.wc, x.ws_ia2, x.ws_ib2, R);
-        for (int d = 0; d < D; ++d) C[d] = fma(x.ws_scale, R[d], C[d]);
+        SF_FOR_DIM(d, D) C[d] = fma(x.ws_scale, R[d], C[d]);
       }
-      for (int d = 0; d < D; ++d) L.Rb[(i * D + d) * TT + tt] = C[d];
+      SF_FOR_DIM(d, D) L.Rb[(i * D + d) * TT + tt] = C[d];
       if (c.vel_on) {
         T v[3], R[3];
-        for (int d = 0; d < D; ++d) v[d] = L.Y[((n + i) * D + d) * TT + tt];
+        SF_FOR_DIM(d, D) v[d] = L.Y[((n + i) * D + d) * TT + tt];
         ball_resid<T>(v, D, x.vmax, R);
-        for (int d = 0; d < D; ++d) L.Rb[((n + i) * D + d) * TT + tt] = R[d];
+        SF_FOR_DIM(d, D) L.Rb[((n + i) * D + d) * TT + tt] = R[d];
       }
       if (c.acc_on) {
         T v[3], R[3];
-        for (int d = 0; d < D; ++d) v[d] = L.Y[((2 * n + i) * D + d) * TT + tt];
+        SF_FOR_DIM(d, D) v[d] = L.Y[((2 * n + i) * D + d) * TT + tt];
         ball_resid<T>(v, D, x.amax, R);
-        for (int d = 0; d < D; ++d) L.Rb[((2 * n + i) * D + d) * TT + tt] = R[d];
+        SF_FOR_DIM(d, D) L.Rb[((2 * n + i) * D + d) * TT + tt] = R[d];
       }
     }
     __syncthreads();
