@@ -63,9 +63,15 @@ def flops_per_sample_iter(cfg):
 
 
 def kernel_source_digest():
+    """SHA-256 over the sources of the MFMA kernel (kernel header, instance files, launcher, shared
+    definitions): a committed traffic summary counts only while this matches."""
+    csrc = os.path.join(ROOT, "paper_2501_19042_amd", "csrc")
+    names = ["sf_fast_kernel.h", "sf_fast.hip", "sf_fast.h", "sf_internal.h", "swarmsf.h"]
+    names += sorted(f for f in os.listdir(csrc) if f.startswith("sf_fast_p") and f.endswith(".hip"))
     h = hashlib.sha256()
-    for f in ("sf_fast.hip", "sf_fast.h", "sf_internal.h"):
-        with open(os.path.join(ROOT, "paper_2501_19042_amd", "csrc", f), "rb") as fh:
+    for f in names:
+        path = os.path.join(csrc, f) if f != "swarmsf.h" else os.path.join(ROOT, "include", f)
+        with open(path, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
@@ -359,7 +365,7 @@ def run_single(args, wl):
     ws = getattr(p.cfg, "ws_a", 0.0) > 0
     config = {"workload": wl.name, "samples": S, "robots": p.cfg.n_robots, "dims": p.cfg.dims,
               "degree": p.cfg.degree, "horizon": p.cfg.horizon, "iters": k_head, "precision": prec,
-              "kernel": "generic" if args.generic else "mfma", "graph": args.graph,
+              "kernel": "generic" if (args.generic or prec == "fp64") else "mfma", "graph": args.graph,
               "launch_shape": "autotuned" if args.autotune else "plan default"}
     if ws:
         config["workspace"] = {"semi_axes": [p.cfg.ws_a, p.cfg.ws_a, p.cfg.ws_b],
