@@ -51,9 +51,10 @@ typedef enum {
   SF_FP32 = 1,          /* everything in single precision */
   SF_BF16 = 2,          /* basis products in bf16 MFMA with the rounding residuals of both factors
                            fed back as fp32-accumulated correction terms; fp32 state */
-  SF_FP16 = 3           /* the same with fp16.  SF_BF16 / SF_FP16 need a batch the MFMA kernels
-                           cover (3D, n_robots <= 32, degree <= 15, horizon <= 256) and no
-                           SF_RESID_HISTORY, else SF_EUNSUPPORTED */
+  SF_FP16 = 3           /* the same with fp16.  SF_BF16 / SF_FP16 apply to the problems the MFMA
+                           kernels cover (3D, n_robots <= 32, degree <= 15, horizon <= 256); the
+                           other problems of the batch run in FP32 (see sf_project).  With
+                           SF_RESID_HISTORY or SF_GENERIC_KERNEL they are SF_EUNSUPPORTED */
 } sf_precision;
 
 /* Flags for sf_project. */
@@ -144,9 +145,11 @@ void sf_destroy(sf_handle h);
  *          (xi^k, lambda^k) at k = 0, c, 2c, ... (c = ckpt_every >= 1), as needed by
  *          sf_project_backward.
  * Aliasing: outputs must not overlap inputs or each other.
- * Kernel choice is per call: SF_FP32 runs on the MFMA kernel when every problem of the batch
- * has a shape it covers (see SF_FP16) that fits its LDS plan, and neither SF_RESID_HISTORY nor
- * SF_GENERIC_KERNEL is set; otherwise the whole batch runs on the generic kernel. */
+ * Kernel choice is per problem: with SF_FP32, SF_BF16 or SF_FP16 the problems of a shape the MFMA
+ * kernels cover (see SF_FP16) that fits their LDS plan run on them, and the other problems of the
+ * batch on the generic kernel in FP32, in a second launch on the same stream (results of every
+ * problem as in a batch of its own kind).  SF_FP64, SF_RESID_HISTORY and SF_GENERIC_KERNEL put the
+ * whole batch on the generic kernel. */
 sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision,
                      const void* xi_bar, const void* bvals,
                      const void* xi0, const void* lam0, int32_t iters,
@@ -159,7 +162,10 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision,
  * resid_out[:, 0] (g_resid, [S]) and of the fixed-point residual sum of SF_FP_RESIDUAL
  * (w_fpr, [S]) -- each may be NULL = zero -- it writes the gradients with respect to
  * xi0, lam0 and xi_bar (each may be NULL = not wanted).  The workspace rows of eq. (f_e) are
- * differentiated like the bound balls (their projection's 3x3 Jacobian). */
+ * differentiated like the bound balls (their projection's 3x3 Jacobian).  The MFMA reverse sweep
+ * serves batches whose every problem the MFMA kernels cover (up to 16 robots, no workspace); any
+ * other batch runs the generic reverse sweep, which recomputes each checkpoint segment with the
+ * generic FP32 (or FP64) iteration. */
 sf_status sf_project_backward(sf_handle h, const sf_batch* batch, int32_t precision,
                               const void* xi_bar, const void* bvals, int32_t iters,
                               const void* ckpt, int32_t ckpt_every,

@@ -227,7 +227,14 @@ struct Plan {
   std::vector<sf::DevProblem> probs;
   std::vector<int32_t> slots_used;
   std::vector<sf::WorkItem> items;      // host copy of the work items
-  sf::FastPlan fast;            // MFMA-path plan (empty if not applicable)
+  // work items of the problems the MFMA kernels cover (d_items_fast is d_items when that is all of
+  // them) and of the others, which run on the generic kernel (none: d_items_gen is NULL)
+  std::vector<sf::WorkItem> items_fast;
+  sf::WorkItem* d_items_fast = nullptr;
+  int32_t n_items_fast = 0;
+  sf::WorkItem* d_items_gen = nullptr;
+  int32_t n_items_gen = 0;
+  sf::FastPlan fast;            // MFMA-path plan over items_fast (empty if there are none)
   sf::FastPlan fast_persistent; // persistent launch of a single-shape batch (built on request)
   // equality-only QP layer: sample chunks per problem (built on first use)
   sf::WorkItem* d_eq_chunks = nullptr;
@@ -265,6 +272,8 @@ void free_plan(Plan* p) {
   for (auto& g : p->graphs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (p->d_probs) (void)hipFree(p->d_probs);
+  if (p->d_items_fast && p->d_items_fast != p->d_items) (void)hipFree(p->d_items_fast);
+  if (p->d_items_gen) (void)hipFree(p->d_items_gen);
   if (p->d_items) (void)hipFree(p->d_items);
   if (p->d_eq_chunks) (void)hipFree(p->d_eq_chunks);
   if (p->d_eq_chunk_first) (void)hipFree(p->d_eq_chunk_first);
@@ -336,7 +345,30 @@ sf_status get_plan(sf_handle h, const sf_batch* batch, Plan** out) {
   std::vector<sf::DevCfg> cfgs;
   for (auto& hc : h->cfgs) cfgs.push_back(hc.dev);
   p->items = items;
-  sf_status st = sf::fast_plan_build(cfgs, p->probs, items, false, p->fast);
+  // split by kernel: problems the MFMA kernels cover, and the others (generic kernel)
+  std::vector<sf::WorkItem> gen;
+  for (const sf::WorkItem& w : items)
+    (sf::fast_cfg_covered(cfgs[p->probs[w.problem].cfg]) ? p->items_fast : gen).push_back(w);
+  p->n_items_fast = (int32_t)p->items_fast.size();
+  p->n_items_gen = (int32_t)gen.size();
+  if (gen.empty()) {
+    p->d_items_fast = p->d_items;
+  } else {
+    e = hipMalloc(&p->d_items_gen, gen.size() * sizeof(sf::WorkItem));
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_items_gen, gen.data(), gen.size() * sizeof(sf::WorkItem), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !p->items_fast.empty()) {
+      e = hipMalloc(&p->d_items_fast, p->items_fast.size() * sizeof(sf::WorkItem));
+      if (e == hipSuccess)
+        e = hipMemcpy(p->d_items_fast, p->items_fast.data(), p->items_fast.size() * sizeof(sf::WorkItem),
+                      hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+      free_plan(p);
+      return hip_fail(e, "plan upload");
+    }
+  }
+  sf_status st = sf::fast_plan_build(cfgs, p->probs, p->items_fast, false, p->fast);
   if (st != SF_OK) {
     free_plan(p);
     return fail(st, "fast plan: " + sf::fast_last_error());
@@ -826,26 +858,37 @@ sf_status sf_project(sf_handle h, const sf_batch* batch, int32_t precision, cons
       if (!p->fast_persistent.ok) {
         std::vector<sf::DevCfg> cfgs;
         for (auto& hc : h->cfgs) cfgs.push_back(hc.dev);
-        st = sf::fast_plan_build(cfgs, p->probs, p->items, true, p->fast_persistent);
+        st = sf::fast_plan_build(cfgs, p->probs, p->items_fast, true, p->fast_persistent);
         if (st != SF_OK) return fail(st, "persistent plan: " + sf::fast_last_error());
       }
       if (p->fast_persistent.ok) fp = &p->fast_persistent;
     }
   }
-  if (precision > SF_FP32 && !fp)
-    return fail(SF_EUNSUPPORTED, "the MFMA precisions need a batch the MFMA kernels cover "
-                                 "(3D, up to 32 robots, degree <= 15, horizon <= 256) and no residual history");
-  if (!fp) {
+  if (precision > SF_FP32 && !fp && (flags & (SF_RESID_HISTORY | SF_GENERIC_KERNEL)))
+    return fail(SF_EUNSUPPORTED, "the MFMA precisions cannot be combined with SF_RESID_HISTORY or SF_GENERIC_KERNEL");
+  // the generic kernel takes every work item without an MFMA plan, else the uncovered ones (if any)
+  const bool gen_part = !fp || p->n_items_gen > 0;
+  if (gen_part) {
     st = pick_tile(h, p, elem, generic_bytes, &a.tile, &a.lds_bytes);
     if (st != SF_OK) return st;
   }
   if (fp && (flags & SF_AUTOTUNE)) {
-    st = autotune(h, p, *fp, a, precision);
+    sf::LaunchArgs af = a;
+    af.items = p->d_items_fast;
+    af.n_items = p->n_items_fast;
+    st = autotune(h, p, *fp, af, precision);
     if (st != SF_OK) return st;
   }
   auto solve = [&](const sf::LaunchArgs& b0) -> hipError_t {
     sf::LaunchArgs b = b0;
-    if (fp) return sf::fast_launch(*fp, b, h->d_tab32, h->d_a16, precision);
+    if (fp) {
+      b.items = p->d_items_fast;
+      b.n_items = p->n_items_fast;
+      const hipError_t fe = sf::fast_launch(*fp, b, h->d_tab32, h->d_a16, precision);
+      if (fe != hipSuccess || p->n_items_gen == 0) return fe;
+      b.items = p->d_items_gen;   // the problems the MFMA kernels do not cover: generic kernel, FP32
+      b.n_items = p->n_items_gen;
+    }
     if (precision == SF_FP64) {
       b.tab = h->d_tab64;
       return sf::launch_generic_project<double>(b);
@@ -930,7 +973,7 @@ sf_status sf_project_backward(sf_handle h, const sf_batch* batch, int32_t precis
   st = get_plan(h, batch, &p);
   if (st != SF_OK) return st;
   int64_t max_ndm = 0;
-  bool fast = precision != SF_FP64 && iters > 0 && p->fast.ok && !(p->fast.ws);
+  bool fast = precision != SF_FP64 && iters > 0 && p->fast.ok && p->n_items_gen == 0 && !(p->fast.ws);
   for (int32_t s : p->slots_used) {
     const sf::DevCfg& c = h->cfgs[s].dev;
     max_ndm = std::max<int64_t>(max_ndm, (int64_t)c.n * c.D * c.m);

@@ -39,6 +39,10 @@ struct FastPlan {
                                         // 2 or 3 waves per workgroup
 };
 
+// Whether the MFMA kernels cover a config: 3D, up to 32 robots, degree <= 15, horizon <= 256, and
+// an LDS plan within 160 KB.
+bool fast_cfg_covered(const DevCfg& c);
+// Plan over the given work items (all of covered configs); `ok` stays false otherwise.
 sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<DevProblem>& probs,
                           const std::vector<WorkItem>& items, bool persistent, FastPlan& out);
 void fast_plan_free(FastPlan& p);

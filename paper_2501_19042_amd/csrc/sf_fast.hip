@@ -126,17 +126,29 @@ double item_cost(const DevCfg& c, int count) {
 
 }  // namespace
 
+bool fast_cfg_covered(const DevCfg& c) {
+  return cfg_supported(c) && (size_t)fast_lds_plan(c, c.n <= 16 ? 1 : 2, 4, 1).total * 4 <= 160 * 1024;
+}
+
 sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<DevProblem>& probs,
                           const std::vector<WorkItem>& items, bool persistent, FastPlan& out) {
   fast_plan_free(out);
   out = FastPlan();
-  if (probs.empty()) return SF_OK;
+  // the problems the work items refer to
+  std::vector<char> used(probs.size(), 0);
+  for (const WorkItem& w : items) used[w.problem] = 1;
+  int first = -1;
+  for (size_t q = 0; q < probs.size() && first < 0; ++q)
+    if (used[q]) first = (int)q;
+  if (first < 0) return SF_OK;
   bool mixed = false;
   int maxKS = 2, maxNT = 1;
-  for (const DevProblem& p : probs) {
+  for (size_t q = 0; q < probs.size(); ++q) {
+    if (!used[q]) continue;
+    const DevProblem& p = probs[q];
     const DevCfg& c = cfgs[p.cfg];
     if (!cfg_supported(c)) return SF_OK;                 // generic path
-    if (p.cfg != probs[0].cfg) mixed = true;
+    if (p.cfg != probs[first].cfg) mixed = true;
     if (c.ws_on) out.ws = true;
     maxKS = std::max(maxKS, (c.m + 3) / 4);
     maxNT = std::max(maxNT, (c.H + 15) / 16);
@@ -146,7 +158,7 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
                                          (size_t)fast_lds_plan(c, c.n <= 16 ? 1 : 2, wi + 2, mp).total * 4);
   }
   if (out.lds_bytes[2][1] > 160 * 1024) return SF_OK;
-  const DevCfg& c0 = cfgs[probs[0].cfg];
+  const DevCfg& c0 = cfgs[probs[first].cfg];
   out.KS = maxKS;
   out.R = c0.n <= 16 ? 1 : 2;
   out.batched = mixed || persistent;

@@ -114,25 +114,46 @@ def test_shapes_past_the_lds_bound_are_refused(P, precision, n, degree):
         gpu_run(P, p, 2, precision)
 
 
-def test_batch_mixing_covered_and_uncovered_shapes(P):
-    """One FP32 call over a 64-robot problem (outside the MFMA kernel's shapes) and a 16-robot
-    problem (inside them): the whole batch runs on the generic kernel with the one-step time tile
-    the larger problem needs, and each problem matches the oracle."""
-    probs = [problem(64, 10, 60, 2), problem(16, 10, 100, 3)]
+def _flat(probs, dt=torch.float32):
+    xb = torch.cat([torch.as_tensor(p.xi_bar, dtype=dt).reshape(-1) for p in probs]).cuda()
+    bv = torch.cat([torch.as_tensor(p.bvals, dtype=dt).reshape(-1) for p in probs]).cuda()
+    return xb, bv
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_batch_mixing_covered_and_uncovered_shapes(P, precision):
+    """One call over a 64-robot problem (outside the MFMA kernels' shapes) and a 16- and a 20-robot
+    problem (inside them): the covered problems run on the MFMA kernels (a persistent launch over
+    their two robot-tile classes) in the requested precision, the 64-robot one on the generic
+    kernel in FP32 with the one-step time tile it needs.  Every problem matches the oracle, and
+    each part is bit for bit the call over that part alone."""
+    probs = [problem(64, 10, 60, 2), problem(16, 10, 100, 3), problem(20, 10, 100, 2)]
     sf = P.SafetyFilter([p.cfg for p in probs])
     batch = P.Batch([(i, p.xi_bar.shape[0]) for i, p in enumerate(probs)])
-    xb = torch.cat([torch.as_tensor(p.xi_bar, dtype=torch.float32).reshape(-1) for p in probs]).cuda()
-    bv = torch.cat([torch.as_tensor(p.bvals, dtype=torch.float32).reshape(-1) for p in probs]).cuda()
+    xb, bv = _flat(probs)
     iters = 6
-    _say(f"case limits mixed batch fp32 n=64+16 iters={iters}")
-    out = sf.project(xb, bv, iters, batch=batch, precision="fp32")
+    _say(f"case limits mixed batch {precision} n=64+16+20 iters={iters}")
+    out = sf.project(xb, bv, iters, batch=batch, precision=precision, want_status=True)
     torch.cuda.synchronize()
+    from paper_2501_19042_amd import _native as N
+    assert ((out.status.cpu() & (N.SF_SAMPLE_NONFINITE | N.SF_SAMPLE_NONFINITE_INPUT)) == 0).all()
+    tol = FP32_TOL if precision == "fp32" else 2e-3
     o = 0
+    parts = []
     for p in probs:
         S = p.xi_bar.shape[0]
         rx, _, _ = oracle_run(p, iters)
-        g = out.xi[o:o + p.xi_bar.size].cpu().double().reshape(S, -1)
+        g = out.xi[o:o + p.xi_bar.size]
+        parts.append(g)
         r = rx.reshape(S, -1)
-        e = ((g - r).abs().amax(1) / r.abs().amax(1)).numpy()
-        assert e.max() <= FP32_TOL, e
+        e = ((g.cpu().double().reshape(S, -1) - r).abs().amax(1) / r.abs().amax(1)).numpy()
+        assert e.max() <= tol, e
         o += p.xi_bar.size
+    # the covered part alone (MFMA kernels, same precision) and the uncovered problem alone (generic, FP32)
+    sf_c = P.SafetyFilter([probs[1].cfg, probs[2].cfg])
+    xc, bc = _flat(probs[1:])
+    oc = sf_c.project(xc, bc, iters, batch=P.Batch([(0, 3), (1, 2)]), precision=precision)
+    og = gpu_run(P, probs[0], iters, "fp32")
+    torch.cuda.synchronize()
+    assert torch.equal(torch.cat(parts[1:]), oc.xi)
+    assert torch.equal(parts[0], og.xi.reshape(-1))
