@@ -106,6 +106,7 @@ __device__ void backproject_tile(const Ctx<T>& x, const T* tile, T* dst, int t0,
   for (int q = threadIdx.x; q < x.nDm; q += blockDim.x) {
     const int row = q / m, kk = q - row * m;
     T acc = T(0);
+#pragma unroll 4
     for (int tt = 0; tt < TTc; ++tt) {
       const size_t brow = (size_t)(t0 + tt) * m + kk;
       acc = fma(x.basis[brow], tile[row * TT + tt], acc);
@@ -283,6 +284,7 @@ adjoint_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, const
             const int row = q / m, kk = q - row * m, f = kk - 3, d = row % D;
             T acc = T(0);
             if (f >= 0 && f < mf) {
+#pragma unroll 4
               for (int f2 = 0; f2 < mf; ++f2) {
                 acc = fma(x.X1[f * mf + f2], gxi[row * m + 3 + f2], acc);
                 acc = fma(x.X01[f * mf + f2], ubar[d * mf + f2], acc);

@@ -150,6 +150,7 @@ feasibility_kernel(const DevCfg* __restrict__ cfgs, const double* __restrict__ t
         const int h = r < 3 ? 0 : c.H - 1;
         const double* brow = basis + ((size_t)bsel * c.H + h) * m;
         double acc = 0.0;
+#pragma unroll 4
         for (int k = 0; k < m; ++k) acc = fma(brow[k], x[row * m + k], acc);
         bmx = fmax(bmx, fabs(acc - (double)bv[row * kNFix + r]));
       }
@@ -160,6 +161,7 @@ feasibility_kernel(const DevCfg* __restrict__ cfgs, const double* __restrict__ t
           const int row = rem / TTc, tt = rem - row * TTc;
           const double* brow = basis + ((size_t)bsel * c.H + t0 + tt) * m;
           double acc = 0.0;
+#pragma unroll 4
           for (int k = 0; k < m; ++k) acc = fma(brow[k], x[row * m + k], acc);
           Y[(bsel * nD + row) * TT + tt] = acc;
         }

@@ -123,6 +123,7 @@ __device__ void eval_tile(const DevCfg& c, const T* __restrict__ basis, const T*
     const T* brow = basis + ((size_t)bsel * c.H + t0 + tt) * c.m;
     const T* x = src + row * c.m;
     T acc = T(0);
+#pragma unroll 4
     for (int k = 0; k < c.m; ++k) acc = fma(brow[k], x[k], acc);
     dst[(bsel * nD + row) * TT + tt] = acc;
   }
@@ -324,6 +325,7 @@ __device__ void iteration(const Ctx<T>& x, const Lds<T>& L, int TT, int k) {
     for (int q = threadIdx.x; q < x.nDm; q += blockDim.x) {
       const int row = q / m, kk = q - row * m;
       T ac = T(0), av = T(0), aa = T(0);
+#pragma unroll 4
       for (int tt = 0; tt < TTc; ++tt) {
         const size_t brow = (size_t)(t0 + tt) * m + kk;
         ac = fma(x.basis[brow], L.Rb[row * TT + tt], ac);
@@ -357,6 +359,7 @@ __device__ void iteration(const Ctx<T>& x, const Lds<T>& L, int TT, int k) {
   for (int q = threadIdx.x; q < x.nDf; q += blockDim.x) {
     const int row = q / mf, f = q - row * mf, d = row % D;
     T acc = T(0);
+#pragma unroll 4
     for (int f2 = 0; f2 < mf; ++f2) {
       acc = fma(x.X1[f * mf + f2], L.ybuf[row * mf + f2], acc);
       acc = fma(x.X01[f * mf + f2], L.ybar[d * mf + f2], acc);
