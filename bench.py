@@ -16,6 +16,7 @@ adjoint, gradient evaluations per second).
 """
 import argparse
 import hashlib
+import statistics
 import json
 import os
 import sys
@@ -94,6 +95,28 @@ def measured_traffic(workload, precision):
     return int(kib * 1024)
 
 
+def measured_counters(workload, precision):
+    """VALU busy, MFMA busy and LDS bank-conflict shares of the MFMA kernel from the committed SQ
+    counter summary, if it was taken on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"fast_project_counters_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    sha, sec, out = None, None, {}
+    for line in open(path):
+        if line.startswith("kernel_source_sha256:"):
+            sha = line.split(":", 1)[1].strip()
+        elif line.startswith("## "):
+            sec = line.split(":", 1)[1].strip().split()[0] if ":" in line else None
+        elif sec == precision and ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            if k in ("valu_busy_pct", "mfma_busy_pct", "lds_bank_conflict_pct_of_cu_cycles"):
+                out[k] = float(v)
+    if sha != kernel_source_digest() or not out:
+        return None
+    out["source"] = os.path.relpath(path, ROOT)
+    return out
+
+
 def host_info():
     """The host the CPU baseline runs on: logical CPUs, the ones this process may use, CPU model."""
     model = "unknown"
@@ -151,24 +174,28 @@ def cpu_baseline(problem, n_samples, iters):
                             "seconds": round(t_tiny, 3)}}
 
 
+LAST_CALLS_MS = []   # per-call times of the last time_calls (event pairs around each call)
+
+
 def time_calls(call, steps, warmup):
     """Run `warmup` untimed calls (at least one: the autotuner, when asked for, runs inside the
     first, and the first launches of a kernel grow its scratch backing), then time exactly `steps`
-    calls with events on the current stream."""
+    calls with events on the current stream: the mean over the bracket is returned, the per-call
+    times are kept in LAST_CALLS_MS."""
     import torch
     out = None
     for _ in range(max(1, warmup)):
         out = call()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for i in range(steps):
         out = call()
-    ev1.record(stream)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
-    return ev0.elapsed_time(ev1) / steps, out
+    LAST_CALLS_MS[:] = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return ev[0].elapsed_time(ev[steps]) / steps, out
 
 
 def judge(sf, out_xi, bv, prec, batch=None):
@@ -360,6 +387,7 @@ def run_single(args, wl):
         if k_eq is not None:
             k_head = k_eq
     ms, out = form(prec, k_head, args.steps, args.warmup)
+    ms_median = statistics.median(LAST_CALLS_MS)
     n_conv, p99, vmax = judge(sf, out.xi, bv, prec)
     traffic = None if (args.generic or prec == "fp64") else measured_traffic(args.workload, prec)
     ws = getattr(p.cfg, "ws_a", 0.0) > 0
@@ -374,9 +402,13 @@ def run_single(args, wl):
         config["safety_semi_axes"] = [p.cfg.safety_a, p.cfg.safety_a, p.cfg.safety_b]
     line = base_line(args, f"converged SF projections/sec ({p.cfg.n_robots} robots, 3D{', workspace' if ws else ''}); "
                      "BF16-MFMA vs FP32 at equal residual", n_conv / (ms / 1e3), ms, DTYPES[prec], config)
-    line.update({"converged_fraction": round(n_conv / S, 6), "violation_p99": p99, "violation_max": vmax,
+    line.update({"ms_per_call_median": round(ms_median, 4),
+                 "converged_fraction": round(n_conv / S, 6), "violation_p99": p99, "violation_max": vmax,
                  "all_samples_per_s": round(S / (ms / 1e3), 1),
                  "roofline": roofline([(p.cfg, S)], k_head, ms, prec, traffic, generic=args.generic)})
+    counters = None if (args.generic or prec == "fp64") else measured_counters(args.workload, prec)
+    if counters:
+        line["roofline"]["counters"] = counters
     if compare:
         line["equal_residual"] = eq
         line["compare"] = {
@@ -430,7 +462,8 @@ def run_ragged(args, wl):
                      {"workload": wl.name, "problems": len(wl.problems), "samples": S,
                       "samples_by_robots": {str(c.n_robots): k for c, k in counts.items()}, "iters": K,
                       "precision": prec, "kernel": "mfma persistent", "graph": True, "autotune": True})
-    line.update({"converged_fraction": round(n_conv / S, 6), "violation_p99": p99, "violation_max": vmax,
+    line.update({"ms_per_call_median": round(ms_median, 4),
+                 "converged_fraction": round(n_conv / S, 6), "violation_p99": p99, "violation_max": vmax,
                  "all_samples_per_s": round(S / (ms / 1e3), 1),
                  "roofline": roofline(list(counts.items()), K, ms, prec, None)})
     return line

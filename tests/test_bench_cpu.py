@@ -59,3 +59,23 @@ def test_equal_residual_search_takes_the_first_k_meeting_every_criterion(monkeyp
     assert k == 302 and all(crit.values()) and first.xi == 300 and len(tried) == 3
     k, crit, _, _ = bench.equal_residual_iters(SF(), None, None, "bf16", 300, (1000, 0.0, 0.0), 303)
     assert k is None and not crit["converged"]
+
+
+def test_counter_and_traffic_summaries_count_only_for_the_current_source(tmp_path, monkeypatch):
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "fast_project_counters_swarm16.txt").write_text(
+        "# header\nkernel_source_sha256: abc\n\n## k<1>: bf16 operands, K = 319\nvalu_busy_pct: 64.8\n"
+        "mfma_busy_pct: 5.6\nlds_bank_conflict_pct_of_cu_cycles: 15.8\n\n## k<0>: fp32 operands, K = 300\n"
+        "valu_busy_pct: 57.1\nmfma_busy_pct: 13.4\nlds_bank_conflict_pct_of_cu_cycles: 13.2\n")
+    (tmp_path / "profiles" / "fast_project_traffic_swarm16_bf16.txt").write_text(
+        "# c\nkernel_source_sha256: abc\nfetch_kib_per_dispatch: 10\nwrite_kib_per_dispatch: 4\n"
+        "fetch_scale: 2.0\nwrite_scale: 1.0\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: "abc")
+    c = bench.measured_counters("swarm16", "fp32")
+    assert c["valu_busy_pct"] == 57.1 and c["mfma_busy_pct"] == 13.4
+    assert bench.measured_counters("swarm16", "bf16")["lds_bank_conflict_pct_of_cu_cycles"] == 15.8
+    assert bench.measured_traffic("swarm16", "bf16") == 24 * 1024
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: "other")
+    assert bench.measured_counters("swarm16", "fp32") is None
+    assert bench.measured_traffic("swarm16", "bf16") is None
