@@ -453,6 +453,7 @@ def run_ragged(args, wl):
                          torch.empty((S, 2), dtype=torch.float32, device="cuda"), None)
     call = lambda: sf.project(xb, bv, K, batch=batch, precision=prec, graph=True, autotune=True, out=bufs)
     ms, out = time_calls(call, args.steps, args.warmup)
+    ms_median = statistics.median(LAST_CALLS_MS)
     n_conv, p99, vmax = judge(sf, out.xi, bv, prec, batch=batch)
     counts = {}
     for p in wl.problems:

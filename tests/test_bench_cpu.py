@@ -79,3 +79,25 @@ def test_counter_and_traffic_summaries_count_only_for_the_current_source(tmp_pat
     monkeypatch.setattr(bench, "kernel_source_digest", lambda: "other")
     assert bench.measured_counters("swarm16", "fp32") is None
     assert bench.measured_traffic("swarm16", "bf16") is None
+
+
+def test_bench_functions_use_no_undefined_names():
+    """Static check (the GPU legs cannot run here): every global name a function of bench.py reads
+    is defined at module level or a builtin."""
+    import builtins
+    import symtable
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    top = symtable.symtable(src, "bench.py", "exec")
+    defined = set(top.get_identifiers())
+    missing = []
+
+    def walk(t):
+        for ch in t.get_children():
+            if ch.get_type() == "function":
+                for s in ch.get_symbols():
+                    nm = s.get_name()
+                    if s.is_global() and not s.is_assigned() and nm not in defined and not hasattr(builtins, nm):
+                        missing.append((ch.get_name(), nm))
+            walk(ch)
+    walk(top)
+    assert not missing, missing
