@@ -198,7 +198,7 @@ def time_calls(call, steps, warmup):
     return ev[0].elapsed_time(ev[steps]) / steps, out
 
 
-def judge(sf, out_xi, bv, prec, batch=None):
+def feasibility_stats(sf, out_xi, bv, prec, batch=None):
     viol = sf.feasibility(out_xi, bv, batch=batch, precision=prec).cpu()
     worst = viol.amax(1)   # collision, velocity, acceleration, boundary, workspace
     feas = worst <= FEAS_TOL
@@ -315,14 +315,14 @@ def run_warmstart(args, wl):
         for K in (25, 50, 100, 200, 300):
             out = sf.project(xb, bv, K, precision=prec, xi0=xi0, lam0=lam0)
             torch.cuda.synchronize()
-            n_conv, p99, vmax = judge(sf, out.xi, bv, prec)
+            n_conv, p99, vmax = feasibility_stats(sf, out.xi, bv, prec)
             r = out.resid[:, 0].double().cpu()
             rows[str(K)] = {"converged_fraction": round(n_conv / S, 4),
                             "resid_sq_median": float(r.median()), "resid_sq_p90": float(r.quantile(0.9)),
                             "violation_p99": p99}
         curves[name] = rows
     ms, out = time_calls(lambda: sf.project(xb, bv, wl.iters, precision=prec), args.steps, args.warmup)
-    n_conv, _, _ = judge(sf, out.xi, bv, prec)
+    n_conv, _, _ = feasibility_stats(sf, out.xi, bv, prec)
     line = base_line(args, f"converged SF projections/sec ({p.cfg.n_robots} robots, 3D); warm-start study",
                      n_conv / (ms / 1e3), ms, DTYPES[prec],
                      {"workload": "warmstart16_3d", "samples": S, "robots": p.cfg.n_robots, "iters": wl.iters,
@@ -342,7 +342,7 @@ def equal_residual_iters(sf, xb, bv, prec, k0, ref, k_max):
         torch.cuda.synchronize()
         if first is None:
             first = out
-        n, p99, vmax = judge(sf, out.xi, bv, prec)
+        n, p99, vmax = feasibility_stats(sf, out.xi, bv, prec)
         crit = {"converged": n >= ref[0], "p99": p99 <= ref[1], "max": vmax <= ref[2]}
         trials.append({"iters": K, "converged": n, "violation_p99": p99, "violation_max": vmax})
         if all(crit.values()):
@@ -378,7 +378,7 @@ def run_single(args, wl):
     k_head, eq = K, None
     if compare:
         ms2, out2 = form(args.compare, K, args.steps, args.warmup)
-        n2, p99b, vmaxb = judge(sf, out2.xi, bv, args.compare)
+        n2, p99b, vmaxb = feasibility_stats(sf, out2.xi, bv, args.compare)
         k_eq, crit, first, trials = equal_residual_iters(sf, xb, bv, prec, K, (n2, p99b, vmaxb),
                                                          K + args.equal_residual_slack)
         dev = ((first.xi - out2.xi).abs().reshape(S, -1).amax(1) / out2.xi.abs().reshape(S, -1).amax(1)).cpu()
@@ -388,7 +388,7 @@ def run_single(args, wl):
             k_head = k_eq
     ms, out = form(prec, k_head, args.steps, args.warmup)
     ms_median = statistics.median(LAST_CALLS_MS)
-    n_conv, p99, vmax = judge(sf, out.xi, bv, prec)
+    n_conv, p99, vmax = feasibility_stats(sf, out.xi, bv, prec)
     traffic = None if (args.generic or prec == "fp64") else measured_traffic(args.workload, prec)
     ws = getattr(p.cfg, "ws_a", 0.0) > 0
     config = {"workload": wl.name, "samples": S, "robots": p.cfg.n_robots, "dims": p.cfg.dims,
@@ -424,7 +424,7 @@ def run_single(args, wl):
         k16, crit16, _, _ = equal_residual_iters(sf, xb, bv, "fp16", K, (n2, p99b, vmaxb), K + args.equal_residual_slack)
         if k16 is not None:
             ms16, out16 = form("fp16", k16, args.steps, args.warmup)
-            n16, _, _ = judge(sf, out16.xi, bv, "fp16")
+            n16, _, _ = feasibility_stats(sf, out16.xi, bv, "fp16")
             line["fp16_form"] = {"iters": k16, "ms_per_step": round(ms16, 4), "value": round(n16 / (ms16 / 1e3), 1),
                                  "converged_fraction": round(n16 / S, 6),
                                  "roofline_frac": roofline([(p.cfg, S)], k16, ms16, "fp16", None)["frac"]}
@@ -454,7 +454,7 @@ def run_ragged(args, wl):
     call = lambda: sf.project(xb, bv, K, batch=batch, precision=prec, graph=True, autotune=True, out=bufs)
     ms, out = time_calls(call, args.steps, args.warmup)
     ms_median = statistics.median(LAST_CALLS_MS)
-    n_conv, p99, vmax = judge(sf, out.xi, bv, prec, batch=batch)
+    n_conv, p99, vmax = feasibility_stats(sf, out.xi, bv, prec, batch=batch)
     counts = {}
     for p in wl.problems:
         counts[p.cfg] = counts.get(p.cfg, 0) + p.xi_bar.shape[0]

@@ -87,7 +87,7 @@ typedef enum {
 #define SF_SAMPLE_NONFINITE_INPUT 1
 #define SF_SAMPLE_NONFINITE 2
 #define SF_SAMPLE_NOT_CONVERGED 4
-#define SF_CONV_TOL 1e-3     /* m, m/s, m/s^2: the feasibility tolerance of the benchmark's judge */
+#define SF_CONV_TOL 1e-3     /* m, m/s, m/s^2: the feasibility tolerance behind the converged count */
 
 /* One problem shape (eqs. poly, inter_robot_con, workspace_con; the velocity and acceleration
  * bounds are origin-centred balls in the polar form of eq. workspace_polar with d in [0, 1]).

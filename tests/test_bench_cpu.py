@@ -52,7 +52,7 @@ def test_equal_residual_search_takes_the_first_k_meeting_every_criterion(monkeyp
     class SF:
         def project(self, xb, bv, K, precision, want_lam):
             return Out(K)
-    monkeypatch.setattr(bench, "judge", lambda sf, xi, bv, prec: trials[xi])
+    monkeypatch.setattr(bench, "feasibility_stats", lambda sf, xi, bv, prec: trials[xi])
     fake_torch = types.SimpleNamespace(cuda=types.SimpleNamespace(synchronize=lambda: None))
     monkeypatch.setitem(sys.modules, "torch", fake_torch)
     k, crit, first, tried = bench.equal_residual_iters(SF(), None, None, "bf16", 300, (995, 1e-3, 5e-3), 310)
