@@ -69,8 +69,11 @@ struct AdjFastArgs {
 bool adjoint_fast_supported(const DevCfg& c);
 size_t adjoint_fast_lds_bytes(const DevCfg& c);
 hipError_t launch_adjoint_fast(const AdjFastArgs& a, int KS);
-// The final-residual term for that path (see sf_adjoint.hip).
-hipError_t launch_adjoint_resid(const AdjointArgs& a, const float* states, int64_t stride, int slot, float* carry,
-                                float* pend);
+// The final-residual term for that path (see sf_adjoint.hip): one workgroup per (sample, time tile
+// of a.tile steps) with per-tile partials in `part` ([n_tiles][2][stride]) and an in-order
+// reduction into the carries (gxi, glam, gxb) and pend.
+size_t adjoint_resid_tile_lds_bytes(const DevCfg& c, int tile);
+hipError_t launch_adjoint_resid_tiles(const AdjointArgs& a, const float* states, int64_t stride, int slot,
+                                      float* part, int n_tiles, float* carry, float* pend);
 
 }  // namespace sf

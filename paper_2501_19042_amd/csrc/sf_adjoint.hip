@@ -17,6 +17,8 @@
 #include "sf_generic_impl.h"
 #include "sf_adjoint.h"
 
+#include <algorithm>
+
 namespace sf {
 namespace {
 
@@ -121,10 +123,11 @@ __device__ void backproject_tile(const Ctx<T>& x, const T* tile, T* dst, int t0,
 // primal_residual), needs L.xprev = xi^{K-1} and L.g = xi^K: adds its cotangent of xi^K to gxi and
 // keeps the one of xi^{K-1} in pend (added after the reverse step of iteration K - 1).
 template <typename T>
-__device__ void resid_term(const Ctx<T>& x, const Lds<T>& L, T* Wt, T* GY, T* gxi, T* pend, T gres, int TT) {
+__device__ void resid_term(const Ctx<T>& x, const Lds<T>& L, T* Wt, T* GY, T* gxi, T* pend, T gres, int TT,
+                           int t_begin = 0, int t_end = 1 << 30) {
   const DevCfg& c = x.c;
   const int n = x.n, D = x.D;
-  for (int t0 = 0; t0 < c.H; t0 += TT) {
+  for (int t0 = t_begin; t0 < min(c.H, t_end); t0 += TT) {
     const int TTc = min(TT, c.H - t0);
     eval_tile<T>(c, x.basis, L.xprev, L.Y, t0, TTc, TT);
     eval_tile<T>(c, x.basis, L.g, Wt, t0, TTc, TT);
@@ -391,48 +394,78 @@ adjoint_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, const
   }
 }
 
-// The final-residual term for the MFMA adjoint path: per sample, from the recomputed states
-// xi^{K-1} (slot `slot` of `states`) and xi^K (slot `slot` + 1), slots 2 * stride elements apart,
-// it initialises the carried cotangents (gxi = g_xi_out + the term's cotangent of xi^K, glam =
-// g_lam_out, gxb = 0; each [stride] in `carry`) and writes pend (the cotangent of xi^{K-1}).
+// The final-residual term for the MFMA adjoint path, from the recomputed states xi^{K-1} (slot
+// `slot` of `states`) and xi^K (slot `slot` + 1), slots 2 * stride elements apart.  One workgroup
+// per (sample, time tile of TT steps): each writes its tile's contributions to the cotangents of
+// xi^K and xi^{K-1} into part ([tile][2][stride]); the reduction kernel below adds them to g_xi_out
+// in tile order (the order in which the generic kernel's resid_term accumulates them over the
+// tiles).  LDS: xi^{K-1}, xi^K, the two tile accumulators and four tile buffers.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-adjoint_resid_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab, const DevProblem* __restrict__ probs,
-                     const WorkItem* __restrict__ items, int n_items, const T* __restrict__ states, int64_t stride,
-                     int slot, const T* __restrict__ g_xi_out, const T* __restrict__ g_lam_out,
-                     const T* __restrict__ g_resid, T* __restrict__ carry, T* __restrict__ pend, int TT) {
+adjoint_resid_tile_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab,
+                          const DevProblem* __restrict__ probs, const WorkItem* __restrict__ items, int n_items,
+                          const T* __restrict__ states, int64_t stride, int slot, const T* __restrict__ g_resid,
+                          T* __restrict__ part, int TT, int n_tiles) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+  for (int wi = blockIdx.x; wi < n_items * n_tiles; wi += gridDim.x) {
+    const int it = wi / n_tiles, tile = wi - it * n_tiles;
     const WorkItem w = items[it];
     const DevProblem pr = probs[w.problem];
     const Ctx<T> x = make_ctx<T>(cfgs[pr.cfg], tab);
-    const Lds<T> L = carve<T>(smem, lds_plan(x.c, TT));
-    const AdjPlan A = adj_plan(x.c, TT);
-    T* gxi = smem + A.gxi;
-    T* pd = smem + A.pend;
-    const int nDm = x.nDm;
+    const int nDm = x.nDm, tsz = 3 * x.n * x.D * TT;
+    Lds<T> L{};
+    L.xprev = smem;
+    L.g = smem + nDm;
+    T* gxi = smem + 2 * nDm;
+    T* pd = smem + 3 * nDm;
+    L.Y = smem + 4 * nDm;
+    L.Rb = L.Y + tsz;
+    T* Wt = L.Rb + tsz;
+    T* GY = Wt + tsz;
+    const int t0 = tile * TT;
     for (int sl = w.first; sl < w.first + w.count; ++sl) {
       const int64_t coef = pr.coef_off + (int64_t)sl * nDm;
       const T gres = g_resid[pr.sample_base + sl];
-      const T* xk1 = states + (int64_t)slot * 2 * stride + coef;
-      const T* xk = xk1 + 2 * stride;
-      for (int q = threadIdx.x; q < nDm; q += blockDim.x) {
-        L.xprev[q] = xk1[q];
-        L.g[q] = xk[q];
-        gxi[q] = g_xi_out ? g_xi_out[coef + q] : T(0);
-        pd[q] = T(0);
+      const bool live = gres != T(0) && t0 < x.c.H;
+      if (live) {
+        const T* xk1 = states + (int64_t)slot * 2 * stride + coef;
+        const T* xk = xk1 + 2 * stride;
+        for (int q = threadIdx.x; q < nDm; q += blockDim.x) {
+          L.xprev[q] = xk1[q];
+          L.g[q] = xk[q];
+          gxi[q] = T(0);
+          pd[q] = T(0);
+        }
+        __syncthreads();
+        resid_term<T>(x, L, Wt, GY, gxi, pd, gres, TT, t0, t0 + TT);
       }
-      __syncthreads();
-      if (gres != T(0)) resid_term<T>(x, L, smem + A.W, smem + A.GY, gxi, pd, gres, TT);
+      T* out = part + (int64_t)tile * 2 * stride + coef;
       for (int q = threadIdx.x; q < nDm; q += blockDim.x) {
-        carry[coef + q] = gxi[q];
-        carry[stride + coef + q] = g_lam_out ? g_lam_out[coef + q] : T(0);
-        carry[2 * stride + coef + q] = T(0);
-        pend[coef + q] = pd[q];
+        out[q] = live ? gxi[q] : T(0);
+        out[stride + q] = live ? pd[q] : T(0);
       }
       __syncthreads();
     }
+  }
+}
+
+// carry = (g_xi_out + the tiles' xi^K cotangents in tile order, g_lam_out, 0), pend = the tiles' xi^{K-1}
+// cotangents in tile order; one thread per coefficient.
+template <typename T>
+__global__ void adjoint_resid_reduce_kernel(int64_t stride, int n_tiles, const T* __restrict__ part,
+                                            const T* __restrict__ g_xi_out, const T* __restrict__ g_lam_out,
+                                            T* __restrict__ carry, T* __restrict__ pend) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < stride; q += (int64_t)gridDim.x * blockDim.x) {
+    T gx = g_xi_out ? g_xi_out[q] : T(0), pe = T(0);
+    for (int t = 0; t < n_tiles; ++t) {
+      gx += part[(int64_t)t * 2 * stride + q];
+      pe += part[((int64_t)t * 2 + 1) * stride + q];
+    }
+    carry[q] = gx;
+    carry[stride + q] = g_lam_out ? g_lam_out[q] : T(0);
+    carry[2 * stride + q] = T(0);
+    pend[q] = pe;
   }
 }
 
@@ -440,16 +473,27 @@ adjoint_resid_kernel(const DevCfg* __restrict__ cfgs, const T* __restrict__ tab,
 
 size_t adjoint_lds_bytes(const DevCfg& c, int tile, size_t elem) { return adj_plan(c, tile).total * elem; }
 
-hipError_t launch_adjoint_resid(const AdjointArgs& a, const float* states, int64_t stride, int slot, float* carry,
-                                float* pend) {
-  auto kern = adjoint_resid_kernel<float>;
+size_t adjoint_resid_tile_lds_bytes(const DevCfg& c, int tile) {
+  const size_t nDm = (size_t)c.n * c.D * c.m;
+  return (4 * nDm + 4 * (size_t)3 * c.n * c.D * tile) * sizeof(float);
+}
+
+hipError_t launch_adjoint_resid_tiles(const AdjointArgs& a, const float* states, int64_t stride, int slot,
+                                      float* part, int n_tiles, float* carry, float* pend) {
+  auto kern = adjoint_resid_tile_kernel<float>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(a.n_items), dim3(kBlock), a.lds_bytes, a.stream, a.cfgs,
-                     static_cast<const float*>(a.tab), a.probs, a.items, a.n_items, states, stride, slot,
-                     static_cast<const float*>(a.g_xi_out), static_cast<const float*>(a.g_lam_out),
-                     static_cast<const float*>(a.g_resid), carry, pend, a.tile);
+  const int64_t n_wg = (int64_t)a.n_items * n_tiles;
+  hipLaunchKernelGGL(kern, dim3((unsigned)std::min<int64_t>(n_wg, 65536)), dim3(kBlock), a.lds_bytes, a.stream,
+                     a.cfgs, static_cast<const float*>(a.tab), a.probs, a.items, a.n_items, states, stride, slot,
+                     static_cast<const float*>(a.g_resid), part, a.tile, n_tiles);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t blocks = std::min<int64_t>((stride + 255) / 256, 16384);
+  hipLaunchKernelGGL(adjoint_resid_reduce_kernel<float>, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0,
+                     a.stream, stride, n_tiles, part, static_cast<const float*>(a.g_xi_out),
+                     static_cast<const float*>(a.g_lam_out), carry, pend);
   return hipGetLastError();
 }
 

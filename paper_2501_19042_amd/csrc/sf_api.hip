@@ -608,7 +608,17 @@ sf_status adjoint_fast_path(sf_handle h, Plan* p, int32_t precision, const void*
                             const void* g_lam_out, const void* g_resid, const void* w_fpr, void* g_xi0, void* g_lam0,
                             void* g_xi_bar, void* stream) {
   const int64_t stride = p->total_coef;
-  const size_t need = ((size_t)2 * (ckpt_every + 1) + 4) * stride * sizeof(float);   // states, carries, pend
+  // final-residual term: one workgroup per (sample, time tile of kResidTile steps), per-tile partials
+  constexpr int kResidTile = 16;
+  int max_h = 1;
+  size_t rlds = 0;
+  for (int32_t sl : p->slots_used) {
+    max_h = std::max(max_h, h->cfgs[sl].dev.H);
+    rlds = std::max(rlds, sf::adjoint_resid_tile_lds_bytes(h->cfgs[sl].dev, kResidTile));
+  }
+  const int n_rtiles = g_resid ? (max_h + kResidTile - 1) / kResidTile : 0;
+  // states, carries, pend, and the residual term's per-tile partials
+  const size_t need = ((size_t)2 * (ckpt_every + 1) + 4 + 2 * (size_t)n_rtiles) * stride * sizeof(float);
   if (need > h->scratch_bytes) {
     if (h->scratch) (void)hipFree(h->scratch);
     h->scratch = nullptr;
@@ -619,6 +629,7 @@ sf_status adjoint_fast_path(sf_handle h, Plan* p, int32_t precision, const void*
   float* states = static_cast<float*>(h->scratch);
   float* carry = states + (size_t)2 * (ckpt_every + 1) * stride;
   float* pend = carry + 3 * stride;
+  float* rpart = pend + stride;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   size_t lds = 0;
   for (int32_t sl : p->slots_used) lds = std::max(lds, sf::adjoint_fast_lds_bytes(h->cfgs[sl].dev));
@@ -657,9 +668,9 @@ sf_status adjoint_fast_path(sf_handle h, Plan* p, int32_t precision, const void*
         ra.g_lam_out = g_lam_out;
         ra.g_resid = g_resid;
         ra.stream = s;
-        sf_status st = pick_tile(h, p, sizeof(float), adj_bytes, &ra.tile, &ra.lds_bytes);
-        if (st != SF_OK) return st;
-        e = sf::launch_adjoint_resid(ra, states, stride, len - 1, carry, pend);
+        ra.tile = kResidTile;
+        ra.lds_bytes = rlds;
+        e = sf::launch_adjoint_resid_tiles(ra, states, stride, len - 1, rpart, n_rtiles, carry, pend);
         if (e != hipSuccess) return hip_fail(e, "sf_project_backward final-residual term");
         pendp = pend;
       } else {
