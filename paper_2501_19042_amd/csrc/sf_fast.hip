@@ -163,14 +163,14 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
   out.R = c0.n <= 16 ? 1 : 2;
   out.batched = mixed || persistent;
   {
-    // default waves per workgroup: 4, unless 2 lets every work item be resident at once
+    // default waves per workgroup (below)
     int dev = 0, ncu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     out.ncu = ncu > 0 ? ncu : 256;
     // resident work items at W waves per workgroup for the register budget of each precision
     auto slots = [&](int W, int mp) {
-      const int by_waves = (4 * waves_per_simd(mixed ? 2 : out.R, mp)) / W;
+      const int by_waves = (4 * waves_per_simd(mixed ? 2 : out.R, mp, W)) / W;
       const int by_lds = (int)((160 * 1024) / std::max<size_t>(out.lds_bytes[W - 2][mp], 1));
       return (int64_t)std::max(1, std::min(by_waves, by_lds)) * out.ncu;
     };
@@ -178,8 +178,20 @@ sf_status fast_plan_build(const std::vector<DevCfg>& cfgs, const std::vector<Dev
     for (int prec = SF_FP32; prec <= SF_FP16; ++prec) {
       const int mp = prec - SF_FP32;
       // the most waves per workgroup that still lets every work item be resident at once; with
-      // more items than that, 2 (the most work items in flight)
-      out.Wp[prec & 3] = ni <= slots(4, mp) ? 4 : (ni <= slots(3, mp) ? 3 : 2);
+      // more items than that, the most waves in flight (the fewer waves per workgroup on a tie,
+      // which keeps more items in flight)
+      int best = ni <= slots(4, mp) ? 4 : (ni <= slots(3, mp) ? 3 : 0);
+      if (best == 0) {
+        int64_t most = -1;
+        for (int W = 2; W <= 4; ++W) {
+          const int64_t waves = std::min(ni, slots(W, mp)) * W;
+          if (waves > most) {
+            most = waves;
+            best = W;
+          }
+        }
+      }
+      out.Wp[prec & 3] = best;
     }
   }
   if (out.batched) {

@@ -93,46 +93,59 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
 // LDS plan (in 4-byte words).  Per-wave tile buffers: positions Xt and collision residual
 // accumulator Ct as [axis][robot (16R)][time] with 16-word rows whose four 16-byte chunks are
 // XOR-swizzled by the robot index (tile_at), so that the 16-byte accesses of 16 consecutive lanes
-// hit distinct banks; boxes bb [robot][kBoxRow]; per tile, the list of pairs that can collide.  Once
+// hit distinct banks; boxes bb [robot][box_row(R)]; per tile, the list of pairs that can collide.  Once
 // its time tiles are done, a wave reuses its own region for its partial back-projection (nDm
 // words) and, after the final residual pass, for its partial sums.
 constexpr int kQPCols = 16;              // QP matrix row in LDS: both halves, each padded (m_f <= 10)
 // Row strides (words) chosen so that the 16-byte accesses of 16 consecutive robots hit 16
-// distinct groups of 4 banks (64 banks): boxes (lo xyz _, hi xyz _, pad) and 16-bit operands.
+// distinct groups of 4 banks (64 banks): boxes (lo xyz _, hi xyz _, pad) and 16-bit operands.  The
+// forward kernel with two robot tiles keeps its boxes unpadded (two-way conflicts in the broad
+// phase, which runs in rebuild iterations only) and its pair lists in 16-bit entries, for an LDS
+// plan that fits two three-wave workgroups per CU.
 constexpr int kBoxRow = 12;
 constexpr int kHBRow = 20;
+__host__ __device__ constexpr int box_row(int R) { return R == 2 ? 8 : kBoxRow; }
 struct FastLds {
   int xi, lam, xb, xprev, dbar, corr, pairs, vmx, amx, wmx, dxi, cmx, qp, hb, tiles, per_wave, total;
   int xt, ct, bb, plist;   // offsets inside one wave's tile region
 };
+// Pair lists of a wave's tiles (count, then pair codes i | j << 8) per tile: 32-bit entries with one
+// robot tile, 16-bit with two.
+__host__ __device__ constexpr int plist_entries(int nr) { return nr * (nr - 1) / 2 + 1; }
+template <int R> struct PairList { typedef int T; };
+template <> struct PairList<2> { typedef uint16_t T; };
 
 __host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W, int MP) {
   const int nDm = c.n * 3 * c.m, nDf = c.n * 3 * c.mf;
   const int nr = 16 * R, Npmax = nr * (nr - 1) / 2;
   FastLds p;
   int o = 0;
+  // (two robot tiles: the previous iterate of the final residual lives in xi_out and the first-step
+  // correction is folded into xi_bar for step 0, so neither takes LDS)
   p.xi = o; o += nDm;
   p.lam = o; o += nDm;
   p.xb = o; o += nDm;
-  p.xprev = o; o += nDm;
+  p.xprev = o; o += R == 1 ? nDm : 0;
   p.dbar = o; o += 3 * kNFix;
-  p.corr = o; o += nDf;
+  p.corr = o; o += R == 1 ? nDf : 0;
   p.pairs = o; o += Npmax;
   p.vmx = o; o += W * nr;                  // per wave and robot: max ||v||^2 over the wave's tiles
   p.amx = o; o += W * nr;                  // same for the acceleration
   p.dxi = o; o += 3 * nr;                  // per (robot, axis): max |change| of a free coefficient
   p.cmx = o; o += 3 * nr;                  // per (robot, axis): max |coefficient| of the iterate
   o = (o + 3) & ~3;
-  p.qp = o; o += 2 * c.mf * kQPCols;       // X1, X01 transposed, rows of at most kQPCols floats
+  // X1, X01 transposed: rows of at most kQPCols floats, or of 4 QC <= 12 floats in the layout of
+  // one robot tile with three waves (QC = 16-byte chunks of the free coefficients)
+  p.qp = o; o += 2 * c.mf * (R == 1 && W == 3 ? 12 : kQPCols);
   o = (o + 3) & ~3;
   p.hb = o; o += MP ? 3 * nr * kHBRow : 0; // 16-bit S1 B operands: [axis][robot][hi x16, lo x16, pad]
   o = (o + 3) & ~3;                        // 16-byte alignment of the tile buffers
   p.xt = 0;
   p.ct = 3 * nr * 16;
   p.bb = 6 * nr * 16;
-  p.plist = p.bb + kBoxRow * nr;           // per tile of the wave: [count, pairs...] kept across iterations
+  p.plist = p.bb + box_row(R) * nr;        // per tile of the wave: [count, pairs...] kept across iterations
   const int NT = (c.H + 15) / 16, TQ = (NT + W - 1) / W;
-  int pw = p.plist + TQ * (Npmax + 1);
+  int pw = p.plist + (R == 2 ? (TQ * plist_entries(nr) + 1) / 2 : TQ * plist_entries(nr));
   if (pw < nDm) pw = nDm;
   if (pw < 128) pw = 128;
   p.per_wave = (pw + 3) & ~3;
@@ -272,6 +285,9 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
   constexpr bool QUART = R == 1 && W == 3;
   constexpr int FQ = (MFX + 3) / 4;                   // free coefficients per lane in that layout
   constexpr int QC = (MFX + 3) / 4;                   // 16-byte chunks of a QP matrix row
+  static_assert(!QUART || 4 * QC <= 12, "QP matrix rows of the quarter layout");
+  // two robot tiles: no LDS copy of the previous iterate or of the first-step correction (see the plan)
+  constexpr bool LEAN = R == 2;
   static_assert(TAILW <= W, "the multiplier/QP step needs 3 x 16R lanes");
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nthr = 64 * W;
@@ -422,7 +438,8 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           acc = fmaf(n_rho_c * Gfx[f * kNFix + r], dl - sdbar[d * kNFix + r], acc);
           acc = fmaf(Rfx[f * kNFix + r], dl, acc);
         }
-        scorr[q] = acc;
+        if constexpr (LEAN) sxb[row * m + 3 + f] += acc;   // step 0 reads xi_bar + correction
+        else scorr[q] = acc;
       }
       __syncthreads();
       // bound-ball drift tracking, lane = robot, identical in every wave: margin to the bound at
@@ -458,7 +475,10 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           }
         }
         if ((resid_out || status_out) && k == iters_s - 1)
-          for (int q = tid; q < nDm; q += nthr) sxprev[q] = sxi[q];
+          for (int q = tid; q < nDm; q += nthr) {
+            if constexpr (LEAN) xi_out[coef + q] = sxi[q];   // overwritten with the result at the end
+            else sxprev[q] = sxi[q];
+          }
         // Velocity/acceleration at every grid time move by at most L * ||max_k |d xi_{i,d,k}| ||_2
         // per step (L = max_t sum_k |basis row|).  While the accumulated drift of every robot stays
         // below its margin to the bound at the last evaluation, the ball residuals are exactly zero
@@ -540,7 +560,10 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         }
         // S1 B operand: xi^T, lane (col, grp) holds robot col, coefficient 4 s + grp
         float bx[MP == 0 ? R : 1][3][KS];
-        typename Half<MP == 0 ? 1 : MP>::V hb1[MP == 0 ? 1 : R][3], hb2[MP == 0 ? 1 : R][3];
+        // (two robot tiles at two waves per SIMD: the 16-bit operands are re-read from LDS per
+        // product instead of held across the tiles, 48 registers fewer)
+        constexpr bool HBR = R == 2 && W == 3;
+        typename Half<MP == 0 ? 1 : MP>::V hb1[MP == 0 || HBR ? 1 : R][3], hb2[MP == 0 || HBR ? 1 : R][3];
         if constexpr (MP == 0) {
 #pragma unroll
           for (int rr = 0; rr < R; ++rr)
@@ -551,7 +574,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                 const int robot = 16 * rr + col, kk = 4 * s + grp;
                 bx[rr][d][s] = (robot < n && kk < m) ? sxi[(robot * 3 + d) * m + kk] : 0.0f;
               }
-        } else {
+        } else if constexpr (!HBR) {
           // lane (col, grp) takes coefficients 8 (grp & 1) .. + 7 of robot col: hi in the first
           // instruction, lo in the second for grp 0, 1 (zero for grp 2, 3; see split_xi)
           typedef typename Half<MP == 0 ? 1 : MP>::V V;
@@ -588,8 +611,15 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
 #pragma unroll
               for (int d = 0; d < 3; ++d) {
                 f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-                acc = mfma16(A1, hb1[rr][d], acc);
-                acc = mfma16(A2, hb2[rr][d], acc);
+                if constexpr (HBR) {
+                  const uint4* hrow = reinterpret_cast<const uint4*>(shb + (d * NR + 16 * rr + col) * (2 * kHBRow));
+                  const uint4 lo = hrow[2 + (grp & 1)];
+                  acc = mfma16(A1, __builtin_bit_cast(V, hrow[grp & 1]), acc);
+                  acc = mfma16(A2, __builtin_bit_cast(V, grp < 2 ? lo : uint4{0u, 0u, 0u, 0u}), acc);
+                } else {
+                  acc = mfma16(A1, hb1[rr][d], acc);
+                  acc = mfma16(A2, hb2[rr][d], acc);
+                }
                 Y[rr][d] = acc;
               }
           }
@@ -628,7 +658,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           // narrow-phase lane mapping: lanes cover (pair, time) items, 64 / T pairs per round with
           // T = the tile's valid times rounded up to 4, 8 or 16.  A list kept from an earlier
           // iteration is read now (count and first round together), ahead of the products.
-          int* tl = reinterpret_cast<int*>(wbuf + L.plist) + q * (NR * (NR - 1) / 2 + 1);
+          typename PairList<R>::T* tl = reinterpret_cast<typename PairList<R>::T*>(wbuf + L.plist) + q * plist_entries(NR);
           const int tsh = nt <= 4 ? 2 : (nt <= 8 ? 3 : 4);
           const int tt = lane & ((1 << tsh) - 1), ps = lane >> tsh, ppr = 64 >> tsh;
           const int kept_count = tl[0], kept_first = tl[1 + ps];
@@ -666,7 +696,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                 hi[d] = grp_max(fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
               }
               if (grp == 0) {
-                float* bq = bb + (16 * rr + col) * kBoxRow;
+                float* bq = bb + (16 * rr + col) * box_row(R);
                 *reinterpret_cast<f4*>(bq) = f4{lo[0], lo[1], lo[2], 0.0f};
                 *reinterpret_cast<f4*>(bq + 4) = f4{hi[0], hi[1], hi[2], 0.0f};
               }
@@ -755,10 +785,10 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           for (int r = 0; r < PR; ++r) {
             const int pij = mypair[r] >= 0 ? mypair[r] : (1 << 8);
             const int i = pij & 255, j = pij >> 8;
-            const f4 li = *reinterpret_cast<const f4*>(bb + i * kBoxRow);
-            const f4 hi = *reinterpret_cast<const f4*>(bb + i * kBoxRow + 4);
-            const f4 lj = *reinterpret_cast<const f4*>(bb + j * kBoxRow);
-            const f4 hj = *reinterpret_cast<const f4*>(bb + j * kBoxRow + 4);
+            const f4 li = *reinterpret_cast<const f4*>(bb + i * box_row(R));
+            const f4 hi = *reinterpret_cast<const f4*>(bb + i * box_row(R) + 4);
+            const f4 lj = *reinterpret_cast<const f4*>(bb + j * box_row(R));
+            const f4 hj = *reinterpret_cast<const f4*>(bb + j * box_row(R) + 4);
             float g2 = 0.0f;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -1012,6 +1042,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           constexpr int QD = FHP > 4 ? 1 : 2;                 // QP rows loaded ahead of their use
           int qq[PF];
           float lp[PF], gr[PF + FH][W], xv[FH], lf[FH], xb[FH], cr[FH];
+          int qx[FH];
           f4 qa[QD][FHP / 4], qb[QD][FHP / 4];
           auto qp_row = [&](int f2, f4 (&a1)[FHP / 4], f4 (&a2)[FHP / 4]) {
             const int rc = max(0, min(f2, mf - 1));
@@ -1032,10 +1063,11 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           for (int j = 0; j < FH; ++j) {
             const int fc = max(0, min(hl * FH + j, mf - 1));
             const int q = row * m + 3 + fc;
+            qx[j] = q;
             xv[j] = sxi[q];
             lf[j] = slam[q];
             xb[j] = sxb[q];
-            cr[j] = scorr[row * (mf > 0 ? mf : 1) + fc];
+            cr[j] = LEAN ? 0.0f : scorr[row * (mf > 0 ? mf : 1) + fc];
 #pragma unroll
             for (int ww = 0; ww < W; ++ww) gr[PF + j][ww] = gp0[ww * L.per_wave + q];
           }
@@ -1061,7 +1093,13 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
             const float g = gsum(PF + j);
             ln[j] = lf[j] - g;
             float yv = xb[j] - xv[j] + ln[j] - g;
-            if (k == 0) yv += cr[j];
+            if (k == 0) {
+              if constexpr (LEAN) {
+                if (on && f < mf) sxb[qx[j]] = xi_bar[coef + qx[j]];   // drop the correction again
+              } else {
+                yv += cr[j];
+              }
+            }
             yo[j] = (on && f < mf) ? yv : 0.0f;
           }
           float ybo[FH];
@@ -1213,7 +1251,8 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
               if (b > 0 && !(b == 1 ? c.vel_on : c.acc_on)) continue;
               const float lim = b == 1 ? vmax : amax;
               f4 Y[R][3];
-              prod(sxprev, tau, b, Y);
+              if constexpr (LEAN) prod(xi_out + coef, tau, b, Y);
+              else prod(sxprev, tau, b, Y);
               if (b == 0) {
 #pragma unroll
                 for (int rr = 0; rr < R; ++rr)
@@ -1372,8 +1411,9 @@ __global__ void reset_queue_kernel(int* queue, int n) {
 
 // Kernel instances: R robot tiles of 16, KS k-steps of 4 coefficients, W waves per workgroup.
 // Target waves per SIMD (the register budget): 3 with one robot tile (168 VGPRs; three waves per
-// sample then keep four samples per CU resident), 1 with two (the whole register file).
-constexpr int waves_per_simd(int R, int MP) { return R == 1 ? 3 : 1; }
+// sample then keep four samples per CU resident); with two robot tiles 2 for three waves per sample
+// (256 VGPRs; two workgroups per CU by LDS, six waves) and 1 otherwise (the whole register file).
+constexpr int waves_per_simd(int R, int MP, int W) { return R == 1 ? 3 : (W == 3 ? 2 : 1); }
 
 FastArgs make_fast_args(const LaunchArgs& a, const float* tab32, const uint4* a16) {
   FastArgs f;
@@ -1389,7 +1429,7 @@ FastArgs make_fast_args(const LaunchArgs& a, const float* tab32, const uint4* a1
 
 template <int R, int KS, int W, int MP, int WS>
 hipError_t launch_instance(const FastPlan& p, const LaunchArgs& a, const float* tab32, const uint4* a16) {
-  auto kern = fast_project_kernel<R, KS, W, MP, waves_per_simd(R, MP), WS>;
+  auto kern = fast_project_kernel<R, KS, W, MP, waves_per_simd(R, MP, W), WS>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes[W - 2][MP]);
   if (e != hipSuccess) return e;
@@ -1400,7 +1440,7 @@ hipError_t launch_instance(const FastPlan& p, const LaunchArgs& a, const float* 
 
 template <int R, int KS, int W, int MP, int WS>
 hipError_t launch_class(const FastClass& C, const FastArgs& f, int grid, int* queue, hipStream_t stream) {
-  auto kern = fast_batched_kernel<R, KS, W, MP, waves_per_simd(R, MP), WS>;
+  auto kern = fast_batched_kernel<R, KS, W, MP, waves_per_simd(R, MP, W), WS>;
   const size_t lds = C.lds_bytes[W - 2][MP];
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
