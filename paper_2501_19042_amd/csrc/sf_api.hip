@@ -383,20 +383,38 @@ sf_status get_plan(sf_handle h, const sf_batch* batch, Plan** out) {
 }
 
 // Largest time tile (<= 32) whose LDS plan fits every config of the plan.
+// Time tile of the generic kernels (one workgroup of kBlock threads per work item): the largest
+// tile of at most 32 steps whose LDS plan fits 80 KB (a one-step tile may take up to 160 KB), unless
+// a smaller one of at least 16 steps keeps more work items resident at once (more workgroups per CU:
+// the headline workload in fp32 runs 75 ms with 32-step tiles, two workgroups per CU, and 46 ms with
+// 16-step tiles, four per CU).  Smaller tiles than that cost more per sample than they gain.
 sf_status pick_tile(sf_handle h, const Plan* p, size_t elem, size_t (*bytes)(const sf::DevCfg&, int, size_t),
                     int* tile, size_t* lds) {
   int maxH = 1;
   for (int32_t s : p->slots_used) maxH = std::max(maxH, h->cfgs[s].dev.H);
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || ncu < 1)
+    ncu = 256;
+  int best = 0;
+  size_t best_lds = 0;
+  int64_t best_res = -1;
   for (int TT = std::min(32, maxH); TT >= 1; TT = (TT > 4 ? TT / 2 : TT - 1)) {
     size_t worst = 0;
     for (int32_t s : p->slots_used) worst = std::max(worst, bytes(h->cfgs[s].dev, TT, elem));
-    if (worst <= 80 * 1024 || (TT == 1 && worst <= 160 * 1024)) {
-      *tile = TT;
-      *lds = worst;
-      return SF_OK;
+    if (!(worst <= 80 * 1024 || (TT == 1 && worst <= 160 * 1024))) continue;
+    const int64_t per_cu = std::max<int64_t>(1, (int64_t)(160 * 1024) / (int64_t)std::max<size_t>(worst, 1));
+    const int64_t res = std::min<int64_t>(p->n_items, per_cu * ncu);
+    if (best == 0 || (TT >= std::min(16, maxH) && res > best_res)) {
+      best = TT;
+      best_lds = worst;
+      best_res = res;
     }
+    if (TT <= std::min(16, maxH)) break;
   }
-  return fail(SF_EUNSUPPORTED, "problem does not fit the LDS plan");
+  if (best == 0) return fail(SF_EUNSUPPORTED, "problem does not fit the LDS plan");
+  *tile = best;
+  *lds = best_lds;
+  return SF_OK;
 }
 
 size_t generic_bytes(const sf::DevCfg& c, int tile, size_t elem) { return sf::generic_lds_bytes(c, tile, elem); }
