@@ -345,3 +345,33 @@ def test_empty_batches_are_refused(lib):
     torch.cuda.synchronize()
     rx, _, _ = run_oracle(p.cfg, p.xi_bar, p.bvals, 5)
     assert_fp64(good.xi, rx, "xi")
+
+
+def test_symmetric_head_on_keeps_its_symmetry_on_the_gpu(lib):
+    """The exactly symmetric 2-robot head-on (2D, generic kernel, FP64; and its 3D lift on the MFMA
+    kernel in fp32): the output keeps x_2 = -x_1 and stays on the line, and matches the oracle."""
+    cfg = W.SwarmConfig(n_robots=2, dims=2, degree=7, horizon=16, t_final=4.0, safety_a=0.3,
+                        safety_b=0.3, vmax=3.0, amax=6.0)
+    st = np.array([[-1.0, 0.0], [1.0, 0.0]])
+    xi_bar = W.straight_line_coeffs(st, -st, cfg.degree)[None]
+    b = W.boundary_values(st, -st)
+    _say("case symmetric head-on fp64 generic")
+    out = gpu_run(lib, cfg, xi_bar, b, 200, "fp64")
+    x = out.xi.cpu().double()[0]
+    assert (x[0] + x[1]).abs().max().item() < 1e-12
+    assert x[:, 1].abs().max().item() < 1e-12
+    rx, _, _ = run_oracle(cfg, xi_bar, b, 200)
+    assert_fp64(out.xi, rx, "symmetric head-on")
+    # 3D, MFMA kernel: the same pair in the plane z = 0
+    cfg3 = W.SwarmConfig(n_robots=2, dims=3, degree=7, horizon=16, t_final=4.0, safety_a=0.3,
+                         safety_b=0.3, vmax=3.0, amax=6.0)
+    st3 = np.array([[-1.0, 0.0, 0.0], [1.0, 0.0, 0.0]])
+    xi3 = W.straight_line_coeffs(st3, -st3, cfg3.degree)[None]
+    b3 = W.boundary_values(st3, -st3)
+    _say("case symmetric head-on fp32 mfma")
+    o3 = gpu_run(lib, cfg3, xi3, b3, 200, "fp32")
+    x3 = o3.xi.cpu().double()[0]
+    assert (x3[0] + x3[1]).abs().max().item() < 1e-6
+    assert x3[:, 1:].abs().max().item() < 1e-6
+    r3, _, _ = run_oracle(cfg3, xi3, b3, 200)
+    assert per_sample_rel(o3.xi, r3).max() <= FP32_TOL

@@ -621,6 +621,30 @@ def test_two_robot_head_on_against_slsqp():
     assert np.sqrt(np.sum((X[0] - X[1]) ** 2, axis=0)).min() >= cfg.safety_a - 1e-3
 
 
+def test_symmetric_head_on_keeps_its_symmetry():
+    """Exactly symmetric head-on (two robots swapping places on a line, no noise): the iteration is
+    equivariant under the point reflection that swaps the robots, so the output keeps x_2 = -x_1
+    and never leaves the line (no lateral avoidance develops; only a perturbation breaks the tie,
+    as in the head-on case above).  The separation at the grid times grows towards the safety
+    distance without reaching it in a finite run: the behaviour is pinned, not feasibility."""
+    cfg = small_cfg(n=2, D=2, degree=7, H=16, T=4.0, vmax=3.0, amax=6.0)
+    st = np.array([[-1.0, 0.0], [1.0, 0.0]])
+    gl = -st
+    xi_bar = W.straight_line_coeffs(st, gl, cfg.degree)[None]
+    b = W.boundary_values(st, gl)
+    s = O.build_system(cfg)
+    P = s.P.numpy()
+    dmins = []
+    for K in (200, 800):
+        out, _, _ = O.sf_project(s, torch.tensor(xi_bar), torch.tensor(b), K)
+        x = out.numpy()[0]
+        assert np.abs(x[0] + x[1]).max() < 1e-12            # point symmetry x_2 = -x_1
+        X = np.einsum("hk,idk->idh", P, x)
+        assert np.abs(X[:, 1]).max() < 1e-12                 # stays on the line
+        dmins.append(np.sqrt(((X[0] - X[1]) ** 2).sum(0)).min())
+    assert dmins[0] < dmins[1] < cfg.safety_a
+
+
 def test_three_robot_crossing_against_slsqp():
     """Three robots in 2D on a unit circle crossing through its centre to the antipodes: the SF
     output is feasible, and its cost is no lower than the local optimum scipy's SLSQP reaches from
