@@ -506,7 +506,7 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["fp64", "fp32", "bf16", "fp16"])
     ap.add_argument("--compare", default="fp32", choices=["fp32", "bf16", "fp16", "none"],
                     help="second form timed beside the headline one")
-    ap.add_argument("--cpu-samples", type=int, default=64)
+    ap.add_argument("--cpu-samples", type=int, default=128)
     ap.add_argument("--equal-residual-slack", type=int, default=60,
                     help="most extra iterations the headline form may take to reach the comparison form's "
                          "final feasibility")
