@@ -100,19 +100,34 @@ constexpr int kQPCols = 16;              // QP matrix row in LDS: both halves, e
 // Row strides (words) chosen so that the 16-byte accesses of 16 consecutive robots hit 16
 // distinct groups of 4 banks (64 banks): boxes (lo xyz _, hi xyz _, pad) and 16-bit operands.  The
 // forward kernel with two robot tiles keeps its boxes unpadded (two-way conflicts in the broad
-// phase, which runs in rebuild iterations only) and its pair lists in 16-bit entries, for an LDS
-// plan that fits two three-wave workgroups per CU.
+// phase, which runs in rebuild iterations only) in the pair-list region, where the list of the tile
+// being rebuilt and those after it are rewritten anyway, its pair lists in 16-bit entries, its pair
+// table in each wave's pair-list region while that is free (set-up, final residual) and its 16-bit
+// operand rows unpadded, with the 16-byte chunks permuted per row instead: an LDS plan that fits
+// two workgroups of three or four waves per CU up to degree 12.
 constexpr int kBoxRow = 12;
 constexpr int kHBRow = 20;
 __host__ __device__ constexpr int box_row(int R) { return R == 2 ? 8 : kBoxRow; }
+__host__ __device__ constexpr int hb_row(int R) { return R == 2 ? 16 : kHBRow; }
+// Word offset of 16-byte chunk ch (0, 1: hi; 2, 3: lo) of the 16-bit operand row `row`
+// (axis * 16R + robot).  Unpadded rows (two robot tiles) permute the chunks by bits 2-3 of the row,
+// so the 16 rows of one lane group still fall in 16 distinct groups of 4 banks.
+template <int R>
+__device__ __forceinline__ int hb_chunk(int row, int ch) {
+  if constexpr (R == 2) return row * 16 + 4 * (ch ^ ((row >> 2) & 3));
+  else return row * kHBRow + 4 * ch;
+}
 struct FastLds {
   int xi, lam, xb, xprev, dbar, corr, pairs, vmx, amx, wmx, dxi, cmx, qp, hb, tiles, per_wave, total;
   int xt, ct, bb, plist;   // offsets inside one wave's tile region
 };
-// Pair lists of a wave's tiles (count, then pair codes i | j << 8) per tile: 32-bit entries with one
-// robot tile, 16-bit with two.
+// Pair table and pair lists of a wave's tiles (count, then pair codes i | j << 8) per tile: 32-bit
+// entries with one robot tile, 16-bit with two.
 __host__ __device__ constexpr int plist_entries(int nr) { return nr * (nr - 1) / 2 + 1; }
 template <int R> struct PairList { typedef int T; };
+// Word offset, from the start of a wave's pair lists, of the boxes of its tile q with two robot tiles:
+// the first 16-byte boundary after the 16-bit lists of tiles 0 .. q - 1.
+__host__ __device__ constexpr int box_at(int q, int nr) { return (((q * plist_entries(nr) + 1) >> 1) + 3) & ~3; }
 template <> struct PairList<2> { typedef uint16_t T; };
 
 __host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W, int MP) {
@@ -128,7 +143,7 @@ __host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W, 
   p.xprev = o; o += R == 1 ? nDm : 0;
   p.dbar = o; o += 3 * kNFix;
   p.corr = o; o += R == 1 ? nDf : 0;
-  p.pairs = o; o += Npmax;
+  p.pairs = o; o += R == 2 ? 0 : Npmax;  // (two robot tiles: in the pair-list regions)
   p.vmx = o; o += W * nr;                  // per wave and robot: max ||v||^2 over the wave's tiles
   p.amx = o; o += W * nr;                  // same for the acceleration
   p.dxi = o; o += 3 * nr;                  // per (robot, axis): max |change| of a free coefficient
@@ -138,14 +153,16 @@ __host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W, 
   // one robot tile with three waves (QC = 16-byte chunks of the free coefficients)
   p.qp = o; o += 2 * c.mf * (R == 1 && W == 3 ? 12 : kQPCols);
   o = (o + 3) & ~3;
-  p.hb = o; o += MP ? 3 * nr * kHBRow : 0; // 16-bit S1 B operands: [axis][robot][hi x16, lo x16, pad]
+  p.hb = o; o += MP ? 3 * nr * hb_row(R) : 0; // 16-bit S1 B operands: [axis][robot][hi x16, lo x16 (, pad)]
   o = (o + 3) & ~3;                        // 16-byte alignment of the tile buffers
   p.xt = 0;
   p.ct = 3 * nr * 16;
-  p.bb = 6 * nr * 16;
-  p.plist = p.bb + box_row(R) * nr;        // per tile of the wave: [count, pairs...] kept across iterations
+  // (two robot tiles: the boxes of tile q sit at the first 16-byte boundary after the pair lists of
+  // tiles 0 .. q - 1, see box_at; the last tile's run past the lists by at most 12 words)
+  p.bb = R == 2 ? 0 : 6 * nr * 16;
+  p.plist = R == 2 ? 6 * nr * 16 : p.bb + box_row(R) * nr;   // per tile of the wave: [count, pairs...] kept across iterations
   const int NT = (c.H + 15) / 16, TQ = (NT + W - 1) / W;
-  int pw = p.plist + (R == 2 ? (TQ * plist_entries(nr) + 1) / 2 : TQ * plist_entries(nr));
+  int pw = p.plist + (R == 2 ? (TQ * plist_entries(nr) + 1) / 2 + 12 : TQ * plist_entries(nr));
   if (pw < nDm) pw = nDm;
   if (pw < 128) pw = 128;
   p.per_wave = (pw + 3) & ~3;
@@ -326,7 +343,16 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
     float* sxprev = smem + L.xprev;
     float* sdbar = smem + L.dbar;
     float* scorr = smem + L.corr;
-    int* spairs = reinterpret_cast<int*>(smem + L.pairs);
+    // pair table, lexicographic (i, j), i < j: shared with one robot tile; with two, each wave's copy
+    // in its pair-list region, written where needed (set-up, final residual)
+    typedef typename PairList<R>::T PT;
+    PT* spairs = reinterpret_cast<PT*>(R == 2 ? smem + L.tiles + wave * L.per_wave + L.plist : smem + L.pairs);
+    auto fill_pairs = [&](int t0, int stride) {
+      for (int i = t0; i < n; i += stride) {
+        int p = i * n - i * (i + 1) / 2;
+        for (int j = i + 1; j < n; ++j) spairs[p++] = static_cast<PT>(i | (j << 8));
+      }
+    };
     float* s_vmx = smem + L.vmx;
     float* s_amx = smem + L.amx;
     float* s_dxi = smem + L.dxi;
@@ -338,8 +364,9 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
     auto put_split = [&](int robot, int d, int kk, float x) {
       const HE hi = static_cast<HE>(x);
       const HE lo = static_cast<HE>(x - static_cast<float>(hi));
-      shb[(d * NR + robot) * (2 * kHBRow) + kk] = hi;
-      shb[(d * NR + robot) * (2 * kHBRow) + 16 + kk] = lo;
+      const int row = d * NR + robot;
+      shb[2 * hb_chunk<R>(row, kk >> 3) + (kk & 7)] = hi;
+      shb[2 * hb_chunk<R>(row, 2 + (kk >> 3)) + (kk & 7)] = lo;
     };
     float* wbuf = smem + L.tiles + wave * L.per_wave;
     float* Xt = wbuf + L.xt;
@@ -353,11 +380,8 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
     };
     auto fixed_k = [&](int r) { return r < 3 ? r : m - kNFix + r; };
 
-    // pair table, lexicographic (i, j), i < j
-    for (int i = tid; i < n; i += nthr) {
-      int p = i * n - i * (i + 1) / 2;
-      for (int j = i + 1; j < n; ++j) spairs[p++] = i | (j << 8);
-    }
+    if constexpr (R == 2) fill_pairs(tid & 63, 64);
+    else fill_pairs(tid, nthr);
     // QP matrices X1 (relative motion) and X01 (mean motion minus relative), transposed and cut
     // into the halves of the outputs the lanes own: [matrix][half][f2][j] = X[half * FH + j][f2]
     // (zero-padded)
@@ -562,7 +586,10 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         float bx[MP == 0 ? R : 1][3][KS];
         // (two robot tiles at two waves per SIMD: the 16-bit operands are re-read from LDS per
         // product instead of held across the tiles, 48 registers fewer)
-        constexpr bool HBR = R == 2 && W == 3;
+        constexpr bool HBR = R == 2 && W >= 3;
+        // word offsets of this lane's hi and lo chunks from the first row of its robot tile and axis
+        // (robot col, chunk grp & 1 and 2 + (grp & 1); see hb_chunk)
+        const int hb_hi = hb_chunk<R>(col, grp & 1), hb_lo = hb_chunk<R>(col, 2 + (grp & 1));
         typename Half<MP == 0 ? 1 : MP>::V hb1[MP == 0 || HBR ? 1 : R][3], hb2[MP == 0 || HBR ? 1 : R][3];
         if constexpr (MP == 0) {
 #pragma unroll
@@ -582,9 +609,9 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           for (int rr = 0; rr < R; ++rr)
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-              const uint4* hrow = reinterpret_cast<const uint4*>(shb + (d * NR + 16 * rr + col) * (2 * kHBRow));
-              hb1[rr][d] = __builtin_bit_cast(V, hrow[grp & 1]);
-              const uint4 lo = hrow[2 + (grp & 1)];
+              const HE* hrow = shb + 2 * (d * NR + 16 * rr) * hb_row(R);
+              hb1[rr][d] = __builtin_bit_cast(V, *reinterpret_cast<const uint4*>(hrow + 2 * hb_hi));
+              const uint4 lo = *reinterpret_cast<const uint4*>(hrow + 2 * hb_lo);
               hb2[rr][d] = __builtin_bit_cast(V, grp < 2 ? lo : uint4{0u, 0u, 0u, 0u});
             }
         }
@@ -612,9 +639,9 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
               for (int d = 0; d < 3; ++d) {
                 f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
                 if constexpr (HBR) {
-                  const uint4* hrow = reinterpret_cast<const uint4*>(shb + (d * NR + 16 * rr + col) * (2 * kHBRow));
-                  const uint4 lo = hrow[2 + (grp & 1)];
-                  acc = mfma16(A1, __builtin_bit_cast(V, hrow[grp & 1]), acc);
+                  const HE* hrow = shb + 2 * (d * NR + 16 * rr) * hb_row(R);
+                  const uint4 lo = *reinterpret_cast<const uint4*>(hrow + 2 * hb_lo);
+                  acc = mfma16(A1, __builtin_bit_cast(V, *reinterpret_cast<const uint4*>(hrow + 2 * hb_hi)), acc);
                   acc = mfma16(A2, __builtin_bit_cast(V, grp < 2 ? lo : uint4{0u, 0u, 0u, 0u}), acc);
                 } else {
                   acc = mfma16(A1, hb1[rr][d], acc);
@@ -659,6 +686,8 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           // T = the tile's valid times rounded up to 4, 8 or 16.  A list kept from an earlier
           // iteration is read now (count and first round together), ahead of the products.
           typename PairList<R>::T* tl = reinterpret_cast<typename PairList<R>::T*>(wbuf + L.plist) + q * plist_entries(NR);
+          // (two robot tiles: over the lists of this tile and the next, which a rebuild rewrites)
+          float* const bbq = R == 2 ? wbuf + L.plist + box_at(q, NR) : bb;
           const int tsh = nt <= 4 ? 2 : (nt <= 8 ? 3 : 4);
           const int tt = lane & ((1 << tsh) - 1), ps = lane >> tsh, ppr = 64 >> tsh;
           const int kept_count = tl[0], kept_first = tl[1 + ps];
@@ -696,7 +725,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                 hi[d] = grp_max(fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
               }
               if (grp == 0) {
-                float* bq = bb + (16 * rr + col) * box_row(R);
+                float* bq = bbq + (16 * rr + col) * box_row(R);
                 *reinterpret_cast<f4*>(bq) = f4{lo[0], lo[1], lo[2], 0.0f};
                 *reinterpret_cast<f4*>(bq + 4) = f4{hi[0], hi[1], hi[2], 0.0f};
               }
@@ -785,10 +814,10 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           for (int r = 0; r < PR; ++r) {
             const int pij = mypair[r] >= 0 ? mypair[r] : (1 << 8);
             const int i = pij & 255, j = pij >> 8;
-            const f4 li = *reinterpret_cast<const f4*>(bb + i * box_row(R));
-            const f4 hi = *reinterpret_cast<const f4*>(bb + i * box_row(R) + 4);
-            const f4 lj = *reinterpret_cast<const f4*>(bb + j * box_row(R));
-            const f4 hj = *reinterpret_cast<const f4*>(bb + j * box_row(R) + 4);
+            const f4 li = *reinterpret_cast<const f4*>(bbq + i * box_row(R));
+            const f4 hi = *reinterpret_cast<const f4*>(bbq + i * box_row(R) + 4);
+            const f4 lj = *reinterpret_cast<const f4*>(bbq + j * box_row(R));
+            const f4 hj = *reinterpret_cast<const f4*>(bbq + j * box_row(R) + 4);
             float g2 = 0.0f;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -1202,6 +1231,14 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
       if (resid_out || status_out) {
         float ss = 0.0f, mx = 0.0f;
         if (iters_s > 0) {
+          if constexpr (R == 2) {
+            // the wave's pair lists are no longer needed (lane index from an opaque copy, so that
+            // nothing of the fill is computed ahead of the iterations)
+            int ln = threadIdx.x & 63;
+            asm volatile("" : "+v"(ln));
+            fill_pairs(ln, 64);
+            wave_sync();
+          }
           // One basis product of a tile for the iterate in `src` (previous or new).  The B operands
           // are formed per product (this runs once per solve), so that only one iterate's
           // products are live at a time.
@@ -1411,9 +1448,10 @@ __global__ void reset_queue_kernel(int* queue, int n) {
 
 // Kernel instances: R robot tiles of 16, KS k-steps of 4 coefficients, W waves per workgroup.
 // Target waves per SIMD (the register budget): 3 with one robot tile (168 VGPRs; three waves per
-// sample then keep four samples per CU resident); with two robot tiles 2 for three waves per sample
-// (256 VGPRs; two workgroups per CU by LDS, six waves) and 1 otherwise (the whole register file).
-constexpr int waves_per_simd(int R, int MP, int W) { return R == 1 ? 3 : (W == 3 ? 2 : 1); }
+// sample then keep four samples per CU resident); with two robot tiles 2 for three or four waves
+// per sample (256 VGPRs; two workgroups per CU by LDS, six or eight waves) and 1 for two (the whole
+// register file).
+constexpr int waves_per_simd(int R, int MP, int W) { return R == 1 ? 3 : (W >= 3 ? 2 : 1); }
 
 FastArgs make_fast_args(const LaunchArgs& a, const float* tab32, const uint4* a16) {
   FastArgs f;
