@@ -158,7 +158,7 @@ __host__ __device__ inline FastLds fast_lds_plan(const DevCfg& c, int R, int W, 
   p.xt = 0;
   p.ct = 3 * nr * 16;
   // (two robot tiles: the boxes of tile q sit at the first 16-byte boundary after the pair lists of
-  // tiles 0 .. q - 1, see box_at; the last tile's run past the lists by at most 12 words)
+  // tiles 0 .. q - 1, see box_at; those of the last tile run past the lists by at most 12 words)
   p.bb = R == 2 ? 0 : 6 * nr * 16;
   p.plist = R == 2 ? 6 * nr * 16 : p.bb + box_row(R) * nr;   // per tile of the wave: [count, pairs...] kept across iterations
   const int NT = (c.H + 15) / 16, TQ = (NT + W - 1) / W;
