@@ -109,13 +109,14 @@ constexpr int kBoxRow = 12;
 constexpr int kHBRow = 20;
 __host__ __device__ constexpr int box_row(int R) { return R == 2 ? 8 : kBoxRow; }
 __host__ __device__ constexpr int hb_row(int R) { return R == 2 ? 16 : kHBRow; }
-// Word offset of 16-byte chunk ch (0, 1: hi; 2, 3: lo) of the 16-bit operand row `row`
-// (axis * 16R + robot).  Unpadded rows (two robot tiles) permute the chunks by bits 2-3 of the row,
-// so the 16 rows of one lane group still fall in 16 distinct groups of 4 banks.
+// Index (16-bit units) of entry e of the 16-bit operand row `row` (axis * 16R + robot): e = kk for
+// the hi part of coefficient kk, 16 + kk for its lo part.  Unpadded rows (two robot tiles) permute
+// their four 16-byte chunks by bits 2-3 of the row, so the 16 rows of one lane group still fall in
+// 16 distinct groups of 4 banks.
 template <int R>
-__device__ __forceinline__ int hb_chunk(int row, int ch) {
-  if constexpr (R == 2) return row * 16 + 4 * (ch ^ ((row >> 2) & 3));
-  else return row * kHBRow + 4 * ch;
+__device__ __forceinline__ int hb_at(int row, int e) {
+  if constexpr (R == 2) return row * 32 + (e ^ (((row >> 2) & 3) << 3));
+  else return row * (2 * kHBRow) + e;
 }
 struct FastLds {
   int xi, lam, xb, xprev, dbar, corr, pairs, vmx, amx, wmx, dxi, cmx, qp, hb, tiles, per_wave, total;
@@ -364,9 +365,8 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
     auto put_split = [&](int robot, int d, int kk, float x) {
       const HE hi = static_cast<HE>(x);
       const HE lo = static_cast<HE>(x - static_cast<float>(hi));
-      const int row = d * NR + robot;
-      shb[2 * hb_chunk<R>(row, kk >> 3) + (kk & 7)] = hi;
-      shb[2 * hb_chunk<R>(row, 2 + (kk >> 3)) + (kk & 7)] = lo;
+      shb[hb_at<R>(d * NR + robot, kk)] = hi;
+      shb[hb_at<R>(d * NR + robot, 16 + kk)] = lo;
     };
     float* wbuf = smem + L.tiles + wave * L.per_wave;
     float* Xt = wbuf + L.xt;
@@ -587,9 +587,9 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
         // (two robot tiles at two waves per SIMD: the 16-bit operands are re-read from LDS per
         // product instead of held across the tiles, 48 registers fewer)
         constexpr bool HBR = R == 2 && W >= 3;
-        // word offsets of this lane's hi and lo chunks from the first row of its robot tile and axis
-        // (robot col, chunk grp & 1 and 2 + (grp & 1); see hb_chunk)
-        const int hb_hi = hb_chunk<R>(col, grp & 1), hb_lo = hb_chunk<R>(col, 2 + (grp & 1));
+        // (two robot tiles: offsets of this lane's hi and lo chunks from the first row of its robot
+        // tile and axis, robot col, entries 8 (grp & 1) and 16 + 8 (grp & 1); see hb_at)
+        const int hb_hi = hb_at<R>(col, 8 * (grp & 1)), hb_lo = hb_at<R>(col, 16 + 8 * (grp & 1));
         typename Half<MP == 0 ? 1 : MP>::V hb1[MP == 0 || HBR ? 1 : R][3], hb2[MP == 0 || HBR ? 1 : R][3];
         if constexpr (MP == 0) {
 #pragma unroll
@@ -609,9 +609,17 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           for (int rr = 0; rr < R; ++rr)
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-              const HE* hrow = shb + 2 * (d * NR + 16 * rr) * hb_row(R);
-              hb1[rr][d] = __builtin_bit_cast(V, *reinterpret_cast<const uint4*>(hrow + 2 * hb_hi));
-              const uint4 lo = *reinterpret_cast<const uint4*>(hrow + 2 * hb_lo);
+              uint4 hi, lo;
+              if constexpr (R == 1) {
+                const uint4* hrow = reinterpret_cast<const uint4*>(shb + (d * NR + 16 * rr + col) * (2 * kHBRow));
+                hi = hrow[grp & 1];
+                lo = hrow[2 + (grp & 1)];
+              } else {
+                const HE* hrow = shb + (d * NR + 16 * rr) * (2 * hb_row(R));
+                hi = *reinterpret_cast<const uint4*>(hrow + hb_hi);
+                lo = *reinterpret_cast<const uint4*>(hrow + hb_lo);
+              }
+              hb1[rr][d] = __builtin_bit_cast(V, hi);
               hb2[rr][d] = __builtin_bit_cast(V, grp < 2 ? lo : uint4{0u, 0u, 0u, 0u});
             }
         }
@@ -639,9 +647,9 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
               for (int d = 0; d < 3; ++d) {
                 f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
                 if constexpr (HBR) {
-                  const HE* hrow = shb + 2 * (d * NR + 16 * rr) * hb_row(R);
-                  const uint4 lo = *reinterpret_cast<const uint4*>(hrow + 2 * hb_lo);
-                  acc = mfma16(A1, __builtin_bit_cast(V, *reinterpret_cast<const uint4*>(hrow + 2 * hb_hi)), acc);
+                  const HE* hrow = shb + (d * NR + 16 * rr) * (2 * hb_row(R));
+                  const uint4 lo = *reinterpret_cast<const uint4*>(hrow + hb_lo);
+                  acc = mfma16(A1, __builtin_bit_cast(V, *reinterpret_cast<const uint4*>(hrow + hb_hi)), acc);
                   acc = mfma16(A2, __builtin_bit_cast(V, grp < 2 ? lo : uint4{0u, 0u, 0u, 0u}), acc);
                 } else {
                   acc = mfma16(A1, hb1[rr][d], acc);
