@@ -1,0 +1,55 @@
+"""The MFMA kernel with two robot tiles (17-32 robots) at every waves-per-sample choice, against the
+FP64 oracle, on shapes that exercise its LDS plan: robot counts that leave phantom robots in the
+second tile, degree 15 (every entry of the 16-bit operand rows in use), and horizons whose time
+tiles fill each wave's share unevenly (one tile per wave, and a last wave with fewer tiles), so the
+boxes of a wave's last tile run past its pair lists and the pair table is rewritten into those
+regions for the final residual."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BOUND = {"fp32": 1e-4, "bf16": 2e-3, "fp16": 2e-4}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2501_19042_amd as P
+    torch.cuda.set_device(0)
+    return P
+
+
+@pytest.mark.parametrize("n,degree,H", [(17, 12, 30), (25, 15, 70), (32, 10, 130)])
+def test_two_tile_shapes_match_oracle(P, tmp_path, monkeypatch, n, degree, H):
+    S, iters = 3, 40
+    p = W.small3d(n_robots=n, n_samples=S, degree=degree, horizon=H, seed=500 + n,
+                  box=((-3.0, -3.0, -1.0), (3.0, 3.0, 1.0)), t_final=10.0)
+    s = O.build_system(p.cfg)
+    rx, _, rr = O.sf_project(s, torch.tensor(p.xi_bar), torch.tensor(p.bvals), iters)
+    xb = torch.tensor(p.xi_bar, dtype=torch.float32).cuda()
+    bv = torch.tensor(p.bvals, dtype=torch.float32).cuda()
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("SWARMSF_TUNE_CACHE", str(cache))
+    for prec in ("fp32", "bf16", "fp16"):
+        cache.write_text("")
+        P.SafetyFilter([p.cfg]).project(xb, bv, 5, precision=prec, autotune=True)
+        torch.cuda.synchronize()
+        key = [l for l in cache.read_text().splitlines() if '"key"' in l][-1].split('"key": "')[1].split('"')[0]
+        for w in (2, 3, 4):
+            cache.write_text('{"key": "%s", "waves": %d, "grid": 0, "ms": 1.0}\n' % (key, w))
+            print(f"case two-tile n={n} deg={degree} H={H} {prec} W={w}", flush=True)
+            out = P.SafetyFilter([p.cfg]).project(xb, bv, iters, precision=prec, autotune=True)
+            torch.cuda.synchronize()
+            g = out.xi.cpu().double().reshape(S, -1)
+            e = ((g - rx.reshape(S, -1)).abs().amax(1) / rx.reshape(S, -1).abs().amax(1)).numpy()
+            print(f"  max rel err {e.max():.2e}", flush=True)
+            assert e.max() <= BOUND[prec], (prec, w, e)
+            # the final residual (pair table rewritten into the pair-list regions) against the
+            # oracle's; the 16-bit forms' iterates differ by up to their bound, so their residuals
+            # get a proportionally looser tolerance
+            tol = dict(rtol=2e-2, atol=1e-6) if prec == "fp32" else dict(rtol=0.25, atol=1e-4)
+            assert torch.allclose(out.resid.cpu().double(), rr, **tol), (prec, w, out.resid, rr)
