@@ -53,3 +53,43 @@ def test_two_tile_shapes_match_oracle(P, tmp_path, monkeypatch, n, degree, H):
             # get a proportionally looser tolerance
             tol = dict(rtol=2e-2, atol=1e-6) if prec == "fp32" else dict(rtol=0.25, atol=1e-4)
             assert torch.allclose(out.resid.cpu().double(), rr, **tol), (prec, w, out.resid, rr)
+
+
+def test_two_tile_persistent_class_mixed_shapes(P, tmp_path, monkeypatch):
+    """One persistent launch over 17-32-robot problems of different degrees and horizons (so each
+    work item has its own LDS plan inside the class kernel), at three and four waves per sample
+    pinned through the autotuner's cache, against the oracle."""
+    probs = [W.small3d(n_robots=n, n_samples=S, degree=deg, horizon=H, seed=600 + k,
+                       box=((-3.0, -3.0, -1.0), (3.0, 3.0, 1.0)), t_final=10.0)
+             for k, (n, deg, H, S) in enumerate([(20, 8, 40, 2), (32, 12, 100, 2), (27, 15, 130, 1)])]
+    iters = 30
+    refs = []
+    for p in probs:
+        s = O.build_system(p.cfg)
+        refs.append(O.sf_project(s, torch.tensor(p.xi_bar), torch.tensor(p.bvals), iters)[0])
+    xb = torch.cat([torch.tensor(p.xi_bar, dtype=torch.float32).reshape(-1) for p in probs]).cuda()
+    bv = torch.cat([torch.tensor(p.bvals, dtype=torch.float32).reshape(-1) for p in probs]).cuda()
+    batch = P.Batch([(i, p.xi_bar.shape[0]) for i, p in enumerate(probs)])
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("SWARMSF_TUNE_CACHE", str(cache))
+    for prec in ("fp32", "bf16"):
+        cache.write_text("")
+        P.SafetyFilter([p.cfg for p in probs]).project(xb, bv, 5, batch=batch, precision=prec, autotune=True)
+        torch.cuda.synchronize()
+        keys = sorted({l.split('"key": "')[1].split('"')[0] for l in cache.read_text().splitlines()})
+        assert len(keys) == 1 and keys[0].endswith(":c0"), keys
+        for w in (3, 4):
+            cache.write_text('{"key": "%s", "waves": %d, "grid": 0, "ms": 1.0}\n' % (keys[0], w))
+            print(f"case two-tile persistent {prec} W={w}", flush=True)
+            out = P.SafetyFilter([p.cfg for p in probs]).project(xb, bv, iters, batch=batch, precision=prec,
+                                                                 autotune=True)
+            torch.cuda.synchronize()
+            assert len(cache.read_text().splitlines()) == 1
+            o = 0
+            for p, rx in zip(probs, refs):
+                S = p.xi_bar.shape[0]
+                g = out.xi[o:o + p.xi_bar.size].reshape(rx.shape).cpu().double()
+                e = ((g - rx).abs().reshape(S, -1).amax(1) / rx.abs().reshape(S, -1).amax(1)).numpy()
+                print(f"  n={p.cfg.n_robots} deg={p.cfg.degree} H={p.cfg.horizon}: max rel err {e.max():.2e}", flush=True)
+                assert e.max() <= BOUND[prec], (prec, w, p.cfg.n_robots, e)
+                o += p.xi_bar.size
