@@ -682,10 +682,11 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           pb = a32c[((wave * 3) * 2 + 1) * 64 + lane];
         }
 
-        // Issue priority (one robot tile): the multiplier/QP step, the barrier after it and the flags
-        // up to here run at priority 2 (each is serial for the sample: all its waves wait on it); in
-        // the tile phase the waves with the most tiles (priority 1) carry the sample's longest path
-        // to the next barrier and the others (0) have slack.  The SIMD issues from the waves of other
+        // Issue priority (one robot tile): from the end of a wave's tiles through the partial write,
+        // the barriers, the multiplier/QP step and the flags up to here, a wave runs at priority 2
+        // (that work is serial for the sample: all its waves wait on it); in the tile phase the waves
+        // with the most tiles (priority 1) carry the sample's longest path to the next barrier and
+        // the others (0) have slack.  The SIMD issues from the waves of other
         // samples in that order, which shortens every sample's iteration.  (The two-tile kernels
         // gain about 1% from it and are left without.)
         if constexpr (R == 1) {
@@ -899,6 +900,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           }
           wave_sync();
         }
+        if constexpr (R == 1) __builtin_amdgcn_s_setprio(2);   // (see the tile phase)
         // this wave's partial back-projection and bound maxima -> its own LDS region
         {
           // Every lane stores, without branches: the rows of phantom robots (past n) fall in the
@@ -927,8 +929,6 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
           }
         }
         __syncthreads();
-        // (issue priority over the other workgroups' waves on the SIMD, see the tile phase)
-        if constexpr (R == 1) __builtin_amdgcn_s_setprio(2);
         // Multiplier step (all coefficients) and QP step (free coefficients) of row (robot, axis):
         // g = F^T rho R summed over the waves, lambda <- lambda - g,
         // y = xi_bar - xi + lambda - g (+ the first-step correction), and
