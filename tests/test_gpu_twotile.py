@@ -93,3 +93,33 @@ def test_two_tile_persistent_class_mixed_shapes(P, tmp_path, monkeypatch):
                 print(f"  n={p.cfg.n_robots} deg={p.cfg.degree} H={p.cfg.horizon}: max rel err {e.max():.2e}", flush=True)
                 assert e.max() <= BOUND[prec], (prec, w, p.cfg.n_robots, e)
                 o += p.xi_bar.size
+
+
+def test_two_tile_workspace_rows_match_oracle(P, tmp_path, monkeypatch):
+    """The two-tile workspace instances (two and three waves per sample), whose boxes share the
+    pair-list region while the workspace residuals go to the tile accumulator, against the oracle."""
+    from dataclasses import replace
+    S, iters = 2, 40
+    p = W.small3d(n_robots=25, n_samples=S, degree=10, horizon=50, seed=700,
+                  box=((-2.5, -2.5, -0.8), (2.5, 2.5, 0.8)), t_final=8.0)
+    cfg = replace(p.cfg, ws_a=2.6, ws_b=0.7, ws_x=0.1)
+    s = O.build_system(cfg)
+    rx, _, _ = O.sf_project(s, torch.tensor(p.xi_bar), torch.tensor(p.bvals), iters)
+    xb = torch.tensor(p.xi_bar, dtype=torch.float32).cuda()
+    bv = torch.tensor(p.bvals, dtype=torch.float32).cuda()
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("SWARMSF_TUNE_CACHE", str(cache))
+    for prec in ("fp32", "bf16"):
+        cache.write_text("")
+        P.SafetyFilter([cfg]).project(xb, bv, 5, precision=prec, autotune=True)
+        torch.cuda.synchronize()
+        key = [l for l in cache.read_text().splitlines() if '"key"' in l][-1].split('"key": "')[1].split('"')[0]
+        for w in (2, 3):
+            cache.write_text('{"key": "%s", "waves": %d, "grid": 0, "ms": 1.0}\n' % (key, w))
+            print(f"case two-tile workspace {prec} W={w}", flush=True)
+            out = P.SafetyFilter([cfg]).project(xb, bv, iters, precision=prec, autotune=True)
+            torch.cuda.synchronize()
+            g = out.xi.cpu().double().reshape(S, -1)
+            e = ((g - rx.reshape(S, -1)).abs().amax(1) / rx.reshape(S, -1).abs().amax(1)).numpy()
+            print(f"  max rel err {e.max():.2e}", flush=True)
+            assert e.max() <= BOUND[prec], (prec, w, e)
