@@ -603,7 +603,9 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
               }
         } else if constexpr (!HBR) {
           // lane (col, grp) takes coefficients 8 (grp & 1) .. + 7 of robot col: hi in the first
-          // instruction, lo in the second for grp 0, 1 (zero for grp 2, 3; see split_xi)
+          // instruction, lo in the second (see split_xi).  The second instruction's A operand is zero
+          // for grp 2, 3, so their lo values (finite: the split of finite coefficients, zero past m)
+          // add exact zeros and need no masking.
           typedef typename Half<MP == 0 ? 1 : MP>::V V;
 #pragma unroll
           for (int rr = 0; rr < R; ++rr)
@@ -620,7 +622,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                 lo = *reinterpret_cast<const uint4*>(hrow + hb_lo);
               }
               hb1[rr][d] = __builtin_bit_cast(V, hi);
-              hb2[rr][d] = __builtin_bit_cast(V, grp < 2 ? lo : uint4{0u, 0u, 0u, 0u});
+              hb2[rr][d] = __builtin_bit_cast(V, lo);   // (grp 2, 3 meet a zero A operand, see below)
             }
         }
         // S1 product for one basis of one tile: Y[rr][d] (lane (col, grp): robot col, times 4 grp + r)
@@ -650,7 +652,7 @@ __device__ __forceinline__ void fast_item(const FastArgs& A, int it, float* smem
                   const HE* hrow = shb + (d * NR + 16 * rr) * (2 * hb_row(R));
                   const uint4 lo = *reinterpret_cast<const uint4*>(hrow + hb_lo);
                   acc = mfma16(A1, __builtin_bit_cast(V, *reinterpret_cast<const uint4*>(hrow + hb_hi)), acc);
-                  acc = mfma16(A2, __builtin_bit_cast(V, grp < 2 ? lo : uint4{0u, 0u, 0u, 0u}), acc);
+                  acc = mfma16(A2, __builtin_bit_cast(V, lo), acc);
                 } else {
                   acc = mfma16(A1, hb1[rr][d], acc);
                   acc = mfma16(A2, hb2[rr][d], acc);
