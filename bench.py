@@ -378,11 +378,12 @@ def run_single(args, wl):
     k_head, eq = K, None
     if compare:
         # the comparison form is the first timed work of the process: bring the device up to its
-        # working clock first (untimed calls for a quarter of a second), so that its figure is not
-        # that of a device still ramping up
+        # working clock first (untimed calls of ten times the iterations for a quarter of a second;
+        # few, long calls, so that a profiler's trace buffer sees few extra dispatches), so that its
+        # figure is not that of a device still ramping up
         t_end = time.perf_counter() + 0.25
         while time.perf_counter() < t_end:
-            sf.project(xb, bv, K, precision=args.compare, generic=args.generic)
+            sf.project(xb, bv, 10 * K, precision=args.compare, generic=args.generic)
             torch.cuda.synchronize()
         ms2, out2 = form(args.compare, K, args.steps, args.warmup)
         n2, p99b, vmaxb = feasibility_stats(sf, out2.xi, bv, args.compare)
